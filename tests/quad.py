@@ -1,0 +1,73 @@
+"""Independent numerical-quadrature references used to pin the oracle.
+
+Nothing here evaluates a Boys function or a recurrence: overlaps and
+electron-repulsion integrals are obtained by Gauss-Hermite quadrature of the
+Gaussian integrands, and the Coulomb operator by
+1/r12 = (2/sqrt(pi)) int_0^inf exp(-t^2 r12^2) dt with adaptive quadrature
+in t (scipy.integrate.quad)."""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial.hermite import hermgauss
+from scipy.integrate import quad
+
+_GH_X, _GH_W = hermgauss(24)
+
+
+def cart_components(l: int) -> list[tuple[int, int, int]]:
+    out = []
+    for i in range(l, -1, -1):
+        for j in range(l - i, -1, -1):
+            out.append((i, j, l - i - j))
+    return out
+
+
+def _pair_1d(i, a, A, j, b, B):
+    """(x-A)^i (x-B)^j exp(-a(x-A)^2 - b(x-B)^2) = K exp(-p (x-P)^2) * poly."""
+    p = a + b
+    P = (a * A + b * B) / p
+    K = np.exp(-a * b / p * (A - B) ** 2)
+    return p, P, K
+
+
+def overlap_1d(i, a, A, j, b, B) -> float:
+    p, P, K = _pair_1d(i, a, A, j, b, B)
+    x = P + _GH_X / np.sqrt(p)
+    f = (x - A) ** i * (x - B) ** j
+    return float(K * np.sum(_GH_W * f) / np.sqrt(p))
+
+
+def overlap_prim(ea, a, A, eb, b, B) -> float:
+    return float(np.prod([overlap_1d(ea[k], a, A[k], eb[k], b, B[k]) for k in range(3)]))
+
+
+def _coulomb_axis(t, i, a, A, j, b, B, k, c, C, l, d, D) -> float:
+    """int int g_ab(x1) g_cd(x2) exp(-t^2 (x1-x2)^2) dx1 dx2 by 2-D Gauss-Hermite
+    after completing the square of the quadratic form."""
+    p, P, K1 = _pair_1d(i, a, A, j, b, B)
+    q, Q, K2 = _pair_1d(k, c, C, l, d, D)
+    t2 = t * t
+    dlt = P - Q
+    M = np.array([[p + t2, -t2], [-t2, q + t2]])
+    bvec = t2 * dlt * np.array([1.0, -1.0])
+    ustar = -np.linalg.solve(M, bvec)
+    const = t2 * dlt * dlt - bvec @ np.linalg.solve(M, bvec)
+    Lc = np.linalg.cholesky(M)
+    LinvT = np.linalg.inv(Lc).T
+    V1, V2 = np.meshgrid(_GH_X, _GH_X, indexing="ij")
+    W = np.outer(_GH_W, _GH_W)
+    U = ustar[:, None, None] + np.einsum("ab,bij->aij", LinvT, np.stack([V1, V2]))
+    x1 = U[0] + P
+    x2 = U[1] + Q
+    f = (x1 - A) ** i * (x1 - B) ** j * (x2 - C) ** k * (x2 - D) ** l
+    return float(K1 * K2 * np.exp(-const) / np.prod(np.diag(Lc)) * np.sum(W * f))
+
+
+def eri_prim(ea, a, A, eb, b, B, ec, c, C, ed, d, D) -> float:
+    def integrand(t):
+        r = 1.0
+        for k in range(3):
+            r *= _coulomb_axis(t, ea[k], a, A[k], eb[k], b, B[k], ec[k], c, C[k], ed[k], d, D[k])
+        return r
+    val, _ = quad(integrand, 0.0, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
+    return float(2.0 / np.sqrt(np.pi) * val)
