@@ -1,0 +1,177 @@
+/*
+ * cq.h -- C ABI of libcq, the MI355X (gfx950) integral-direct Coulomb /
+ * exchange build.
+ *
+ * What is computed (paper: "Reference Wave Functions", Eq. 2c_fock, and the
+ * integral-direct statement that follows it; "General Infrastructure for the
+ * Unified Treatment of Electronic Spin", Eqs. pauli_sep, spin_generalization,
+ * 2c_expectation):
+ *
+ *   J[X]_{mn} = sum_{ls} (mn|ls) X_{ls}          K[X]_{mn} = sum_{ls} (ml|ns) X_{ls}
+ *
+ * with (mn|ls) the electron-repulsion integrals over contracted Cartesian
+ * Gaussian shells (paper: Introduction, LCAO over contracted Gaussian-type
+ * orbitals), recomputed on every call (direct SCF) and never stored.
+ *
+ * Conventions for every entry point
+ * - Units: bohr, hartree, atomic units of time.
+ * - Matrices are contiguous row-major double [nbf][nbf] in DEVICE memory,
+ *   owned by the caller; the library never frees them.  Outputs must not
+ *   alias inputs.
+ * - Functions are ordered shell by shell in the order given to
+ *   cq_basis_create; within a shell, Cartesian components are lexicographic
+ *   (l=1: x y z; l=2: xx xy xz yy yz zz), each normalized to unit self-overlap.
+ * - Work is enqueued on the given stream (NULL = the default stream) and is
+ *   asynchronous unless stated.  A handle must not be used from two streams
+ *   at the same time.
+ * - Every function returns a cq_status; on failure, cq_last_error() gives a
+ *   message (thread-local).  Argument errors are detected before any work
+ *   is enqueued.
+ */
+#ifndef CQ_H
+#define CQ_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CQ_OK = 0,
+    CQ_EINVAL = 1,        /* invalid argument */
+    CQ_ENOMEM = 2,        /* device or host allocation failed */
+    CQ_EHIP = 3,          /* a HIP runtime call failed */
+    CQ_EUNSUPPORTED = 4,  /* angular momentum above d, or a feature not built */
+    CQ_ENONFINITE = 5,    /* a non-finite value was found in an input density */
+    CQ_ENOTCONV = 6       /* an iterative step did not converge */
+} cq_status;
+
+typedef struct cq_basis_s* cq_basis;
+
+/* Thresholds of one build.
+ *   skip:       quartets whose bound Q_ab Q_cd max|X| (Schwarz factors times
+ *               the largest density element of the six shell blocks the
+ *               quartet touches, maximized over all densities; the paper's
+ *               LinK-like screening, "Reference Wave Functions") is below
+ *               this value are not evaluated.  0 = no screening (exact).
+ *   fp32_below: in mode 1, quartet batches whose bound is below this value
+ *               are evaluated in FP32 (with compensated accumulation).
+ *   mode:       0 = FP64 throughout; 1 = precision-routed.
+ *   flags:      CQ_ACCUMULATE adds into J/K instead of overwriting them. */
+typedef struct {
+    double skip;
+    double fp32_below;
+    int mode;
+    unsigned flags;
+} cq_thresholds;
+
+#define CQ_ACCUMULATE 1u
+#define CQ_MAX_DENSITIES 16
+
+/* Thread-local message describing the last failure ("" if none). */
+const char* cq_last_error(void);
+
+/* Create a basis from host arrays (copied; the caller keeps ownership).
+ *   nshell          number of shells (>= 1)
+ *   xyz[nshell*3]   shell centers (bohr)
+ *   l[nshell]       angular momentum, 0..2
+ *   nprim[nshell]   primitives per shell, 1..8
+ *   alpha[], coef[] exponents and raw contraction coefficients, concatenated
+ *                   shell by shell (sum(nprim) entries)
+ * Each contracted function is normalized (paper: Introduction, contracted
+ * Gaussian-type orbitals): primitives carry (2a/pi)^{3/4}(4a)^{l/2}/sqrt((2l-1)!!),
+ * the contraction is rescaled to unit self-overlap of x^l, and each Cartesian
+ * component x^i y^j z^k gets sqrt((2l-1)!!/((2i-1)!!(2j-1)!!(2k-1)!!)).
+ * Allocates library-owned device memory; synchronizes `stream`.  The Schwarz
+ * factors are computed here (see cq_schwarz). */
+cq_status cq_basis_create(int nshell, const double* xyz, const int* l, const int* nprim,
+                          const double* alpha, const double* coef, hipStream_t stream,
+                          cq_basis* out);
+
+/* Release a basis and all of its device memory (synchronizes the device). */
+cq_status cq_basis_destroy(cq_basis b);
+
+/* Number of basis functions / shells of a basis (-1 on a NULL handle). */
+int cq_basis_nbf(cq_basis b);
+int cq_basis_nshell(cq_basis b);
+
+/* Schwarz factors Q_ab = sqrt(max_{m in a, n in b} (mn|mn)) (paper:
+ * "Reference Wave Functions", integral screening).  Computed once at basis
+ * creation and cached.  If Q is not NULL, the [nshell][nshell] matrix is
+ * copied to the DEVICE buffer Q (stream-ordered). */
+cq_status cq_schwarz(cq_basis b, double* Q, hipStream_t stream);
+
+/* Coulomb and exchange matrices of nmat densities in one integral pass.
+ *   nmat        1..CQ_MAX_DENSITIES
+ *   P[nmat]     host array of device pointers to the densities X_m
+ *   sym[nmat]   +1 if X_m is symmetric, -1 if antisymmetric (only that part
+ *               of X_m is used; e.g. the imaginary part of a Hermitian
+ *               density is antisymmetric, paper: the remark on the
+ *               symmetry of X^I after Eq. spin_generalization)
+ *   J[nmat]     host array of device output pointers; an entry may be NULL
+ *               (no Coulomb matrix wanted); must be NULL where sym = -1
+ *               (J of an antisymmetric density vanishes).  J itself may be
+ *               NULL (no Coulomb matrices at all).
+ *   K[nmat]     same for exchange; K may be NULL.
+ *   th          thresholds (NULL = exact FP64, overwrite)
+ * No Fock factors are applied: J and K are the bare contractions above.
+ * Asynchronous on `stream`. */
+cq_status cq_jk_build(cq_basis b, int nmat, const double* const* P, const int* sym,
+                      double* const* J, double* const* K, const cq_thresholds* th,
+                      hipStream_t stream);
+
+/* Two-electron part of the two-component (generalized spin) Fock matrix
+ * (paper: Eq. pauli_sep and Eq. 2c_fock, with G^0 = 2 J[P^0] - K[P^0] and
+ * G^k = -K[P^k]; the factor 2 follows from the 1/2 in Eq. pauli_sep):
+ *   P2c   device, complex Hermitian spin-blocked density [[aa, ab],[ba, bb]],
+ *         2nbf x 2nbf, interleaved (re, im) doubles, row-major
+ *   G2c   device output, same layout: sum_I sigma_I (x) G^I
+ * P2c is split into the real symmetric Re P^I and antisymmetric Im P^I
+ * (I = 0..3); J is formed for Re P^0 and K for all eight in one integral
+ * pass.  Asynchronous on `stream`. */
+cq_status cq_fock2e_2c(cq_basis b, const double* P2c, double* G2c, const cq_thresholds* th,
+                       hipStream_t stream);
+
+
+/* One-electron integrals over the basis, written to the DEVICE matrix out
+ * [nbf][nbf] (setup of the real-time path; paper: "Real-Time Electronic
+ * Dynamics", Eqs. td_pert / td_expectation use a core Hamiltonian, a metric
+ * and one-body field / observable operators):
+ *   kind 0  overlap      S_mn = <m|n>
+ *   kind 1  kinetic      T_mn = -1/2 <m|lap|n>
+ *   kind 2  dipole       <m| r_dir - origin_dir |n>, dir = 0,1,2 (x,y,z)
+ *   kind 3  nuclear      V_mn = -sum_C Z_C <m| 1/|r - R_C| |n>
+ * origin (host, 3 doubles) may be NULL (= 0); Z[ncharge] and cxyz[3*ncharge]
+ * are host arrays used only by kind 3.  Asynchronous on `stream` except for
+ * kind 3, which synchronizes it. */
+cq_status cq_one_electron(cq_basis b, int kind, int dir, const double* origin, int ncharge,
+                          const double* Z, const double* cxyz, double* out, hipStream_t stream);
+
+/* Number of unique contracted shell quartets per class for an unscreened
+ * build (bra pair >= ket pair; la>=lb, lc>=ld).  For entry k < maxn:
+ * cls[4k..4k+3] = (la, lb, lc, ld), count[k]; *n = number of classes. */
+cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, int* n);
+
+/* Per-class launch timing with HIP events recorded on the launch stream
+ * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.
+ * cq_profile_read synchronizes on the recorded events and returns, per class
+ * that ran, cls[4k..4k+3], the summed kernel time ms[k] and launch count
+ * count[k]; *n = number of such classes. */
+cq_status cq_profile(cq_basis b, int enable);
+cq_status cq_profile_read(cq_basis b, int maxn, int* cls, double* ms, long long* count, int* n);
+
+/* ---- test-only exports ------------------------------------------------ */
+
+/* Boys function F_m(T) for m = 0..mmax (mmax <= 16) at n points, FP64.
+ * T: device [n]; F: device [n][mmax+1].  Asynchronous on `stream`. */
+cq_status cq_boys(int mmax, int n, const double* T, double* F, hipStream_t stream);
+
+/* One contracted, normalized shell-quartet block (ab|cd), layout
+ * [na][nb][nc][nd], written to HOST memory `out` (synchronizes `stream`). */
+cq_status cq_eri_quartet(cq_basis b, int a, int bsh, int c, int d, double* out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQ_H */

@@ -1,0 +1,236 @@
+"""Thin Python binding of libcq (include/cq.h): argument marshalling only.
+
+Every computation runs in the HIP library.  PyTorch provides device memory
+and streams; the library raises ``RuntimeError`` if it is missing or was not
+built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcq.so")
+
+CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EHIP, CQ_EUNSUPPORTED, CQ_ENONFINITE, CQ_ENOTCONV = range(7)
+CQ_ACCUMULATE = 1
+CQ_MAX_DENSITIES = 16
+_STATUS = {0: "CQ_OK", 1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EHIP", 4: "CQ_EUNSUPPORTED",
+           5: "CQ_ENONFINITE", 6: "CQ_ENOTCONV"}
+
+_lib = None
+
+
+class CqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Thresholds(ctypes.Structure):
+    _fields_ = [("skip", ctypes.c_double), ("fp32_below", ctypes.c_double),
+                ("mode", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+def lib():
+    """Load libcq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcq.so not found at {LIB_PATH}; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip, i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int
+        L.cq_last_error.restype = ctypes.c_char_p
+        L.cq_basis_create.argtypes = [i, dp, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
+        L.cq_basis_destroy.argtypes = [vp]
+        L.cq_basis_nbf.argtypes = [vp]
+        L.cq_basis_nbf.restype = i
+        L.cq_basis_nshell.argtypes = [vp]
+        L.cq_basis_nshell.restype = i
+        L.cq_schwarz.argtypes = [vp, vp, vp]
+        L.cq_jk_build.argtypes = [vp, i, ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(Thresholds), vp]
+        L.cq_fock2e_2c.argtypes = [vp, vp, vp, ctypes.POINTER(Thresholds), vp]
+        L.cq_boys.argtypes = [i, i, vp, vp, vp]
+        L.cq_eri_quartet.argtypes = [vp, i, i, i, i, dp, vp]
+        L.cq_one_electron.argtypes = [vp, i, i, dp, i, dp, dp, vp, vp]
+        llp = ctypes.POINTER(ctypes.c_longlong)
+        L.cq_quartet_counts.argtypes = [vp, i, ip, llp, ip]
+        L.cq_profile.argtypes = [vp, i]
+        L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
+        for name in ("cq_basis_create", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
+                     "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile",
+                     "cq_profile_read"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != CQ_OK:
+        raise CqError(status, lib().cq_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _req_dev(t, dtype, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass
+class JKResult:
+    J: list
+    K: list
+
+
+def thresholds(skip: float = 0.0, fp32_below: float = 0.0, mode: int = 0, accumulate: bool = False) -> Thresholds:
+    return Thresholds(float(skip), float(fp32_below), int(mode), CQ_ACCUMULATE if accumulate else 0)
+
+
+class Basis:
+    """A libcq basis handle (device resident)."""
+
+    def __init__(self, shell_xyz, shell_l, nprim, alpha, coef, stream=None):
+        xyz = np.ascontiguousarray(shell_xyz, dtype=np.float64).reshape(-1)
+        l = np.ascontiguousarray(shell_l, dtype=np.int32)
+        npr = np.ascontiguousarray(nprim, dtype=np.int32)
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        h = ctypes.c_void_p()
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        _check(lib().cq_basis_create(int(l.size), xyz.ctypes.data_as(dp), l.ctypes.data_as(ip),
+                                     npr.ctypes.data_as(ip), a.ctypes.data_as(dp), c.ctypes.data_as(dp),
+                                     _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.nbf = lib().cq_basis_nbf(h)
+        self.nshell = lib().cq_basis_nshell(h)
+        self.shell_l = l.copy()
+
+    @classmethod
+    def from_molecule(cls, mol, stream=None) -> "Basis":
+        return cls(mol.shell_xyz, mol.shell_l, mol.nprim, mol.alpha, mol.coef, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().cq_basis_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def schwarz(self, stream=None):
+        import torch
+        Q = torch.empty((self.nshell, self.nshell), dtype=torch.float64, device="cuda")
+        _check(lib().cq_schwarz(self.h, _ptr(Q), _stream(stream)))
+        return Q
+
+    def jk(self, P, sym=None, want_j=True, want_k=True, th: Thresholds | None = None, out=None, stream=None):
+        """J[X_m], K[X_m] for a list of densities (device float64 [nbf, nbf]).
+        ``want_j`` / ``want_k``: bool or per-density list of bools."""
+        import torch
+        Ps = list(P) if isinstance(P, (list, tuple)) else [P]
+        n = len(Ps)
+        sym = [1] * n if sym is None else list(sym)
+        wj = [want_j] * n if isinstance(want_j, bool) else list(want_j)
+        wk = [want_k] * n if isinstance(want_k, bool) else list(want_k)
+        for p in Ps:
+            _req_dev(p, torch.float64, (self.nbf, self.nbf))
+        if out is None:
+            J = [torch.empty_like(Ps[m]) if wj[m] else None for m in range(n)]
+            K = [torch.empty_like(Ps[m]) if wk[m] else None for m in range(n)]
+        else:
+            J, K = out
+        arr = ctypes.c_void_p * max(n, 1)
+        pP = arr(*[p.data_ptr() for p in Ps])
+        pJ = arr(*[(j.data_ptr() if j is not None else 0) for j in J])
+        pK = arr(*[(k.data_ptr() if k is not None else 0) for k in K])
+        psym = (ctypes.c_int * n)(*sym)
+        thp = ctypes.byref(th) if th is not None else None
+        _check(lib().cq_jk_build(self.h, n, pP, psym, pJ, pK, thp, _stream(stream)))
+        return JKResult(J, K)
+
+    def fock2e_2c(self, P2c, th: Thresholds | None = None, out=None, stream=None):
+        """G^{2C} (complex128 [2nbf, 2nbf]) of a spin-blocked density."""
+        import torch
+        _req_dev(P2c, torch.complex128, (2 * self.nbf, 2 * self.nbf))
+        G = torch.empty_like(P2c) if out is None else out
+        thp = ctypes.byref(th) if th is not None else None
+        _check(lib().cq_fock2e_2c(self.h, _ptr(P2c), _ptr(G), thp, _stream(stream)))
+        return G
+
+    def one_electron(self, kind: str, direction: int = 2, origin=(0.0, 0.0, 0.0), charges=None,
+                     centers=None, stream=None):
+        """S, T, V or a dipole component as a device float64 [nbf, nbf]."""
+        import torch
+        k = {"overlap": 0, "kinetic": 1, "dipole": 2, "nuclear": 3}[kind]
+        out = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device="cuda")
+        dp = ctypes.POINTER(ctypes.c_double)
+        org = np.ascontiguousarray(origin, dtype=np.float64)
+        if k == 3:
+            Z = np.ascontiguousarray(charges, dtype=np.float64)
+            C = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1)
+            nz = int(Z.size)
+            zp, cp = Z.ctypes.data_as(dp), C.ctypes.data_as(dp)
+        else:
+            nz, zp, cp = 0, None, None
+        _check(lib().cq_one_electron(self.h, k, int(direction), org.ctypes.data_as(dp), nz, zp, cp,
+                                     _ptr(out), _stream(stream)))
+        return out
+
+    def quartet_counts(self) -> dict:
+        """{(la, lb, lc, ld): unique shell quartets of an unscreened build}."""
+        n = ctypes.c_int()
+        cls = (ctypes.c_int * 256)()
+        cnt = (ctypes.c_longlong * 64)()
+        _check(lib().cq_quartet_counts(self.h, 64, cls, cnt, ctypes.byref(n)))
+        return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
+
+    def profile(self, enable: bool = True, reset: bool = False):
+        _check(lib().cq_profile(self.h, 2 if (enable and reset) else int(enable)))
+
+    def profile_read(self) -> dict:
+        """{(la, lb, lc, ld): (total kernel ms, launches)} from HIP events."""
+        n = ctypes.c_int()
+        cls = (ctypes.c_int * 256)()
+        ms = (ctypes.c_double * 64)()
+        cnt = (ctypes.c_longlong * 64)()
+        _check(lib().cq_profile_read(self.h, 64, cls, ms, cnt, ctypes.byref(n)))
+        return {tuple(cls[4 * k: 4 * k + 4]): (float(ms[k]), int(cnt[k])) for k in range(n.value)}
+
+    def eri_quartet(self, a, b, c, d, stream=None) -> np.ndarray:
+        n = [(int(self.shell_l[s]) + 1) * (int(self.shell_l[s]) + 2) // 2 for s in (a, b, c, d)]
+        out = np.zeros(n)
+        _check(lib().cq_eri_quartet(self.h, int(a), int(b), int(c), int(d),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)))
+        return out
+
+
+def boys(mmax: int, T, stream=None):
+    """F_m(T), m = 0..mmax, for a device float64 vector T -> [n, mmax+1]."""
+    import torch
+    _req_dev(T, torch.float64)
+    F = torch.empty((T.numel(), mmax + 1), dtype=torch.float64, device=T.device)
+    _check(lib().cq_boys(int(mmax), int(T.numel()), _ptr(T), _ptr(F), _stream(stream)))
+    return F

@@ -1,0 +1,163 @@
+// Device-side types and helpers shared by the generated electron-repulsion
+// kernels and the hand-written support kernels of libcq.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CQ_MAX_MAT 16
+
+// ---------------------------------------------------------------------------
+// Boys function F_m(T), m = 0..L, FP64.
+// T < BOYS_TC: F_L from a Chebyshev interpolant on intervals of width
+// BOYS_H (degree BOYS_NC-1), then the downward recursion
+// F_m = (2T F_{m+1} + exp(-T)) / (2m+1), which is stable.
+// T >= BOYS_TC: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to 2e-17 there) and the
+// upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T), stable for T > m.
+// ---------------------------------------------------------------------------
+#define BOYS_TC 36.0
+#define BOYS_H 0.5
+#define BOYS_NINT 72
+#define BOYS_NC 10
+#define BOYS_LMAX 16
+
+__device__ __forceinline__ double rsqrt_f64(double x) { return rsqrt(x); }
+
+template <int L>
+__device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ tab, double* F)
+{
+    if (T < BOYS_TC) {
+        int k = (int)(T * (1.0 / BOYS_H));
+        k = k < 0 ? 0 : (k > BOYS_NINT - 1 ? BOYS_NINT - 1 : k);
+        const double x = (T - k * BOYS_H) * (2.0 / BOYS_H) - 1.0;
+        const double* c = tab + ((size_t)L * BOYS_NINT + k) * BOYS_NC;
+        double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+        for (int j = BOYS_NC - 1; j >= 1; --j) {
+            const double b0 = fma(2.0 * x, b1, c[j] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        F[L] = fma(x, b1, c[0] - b2);
+        if (L > 0) {
+            const double e = exp(-T);
+            const double t2 = 2.0 * T;
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
+        }
+    } else {
+        F[0] = 0.88622692545275801365 * rsqrt_f64(T);  // sqrt(pi)/2 / sqrt(T)
+        if (L > 0) {
+            const double e = exp(-T);
+            const double h = 0.5 / T;
+#pragma unroll
+            for (int m = 0; m < L; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * h;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shell-pair data of one pair class (la >= lb), structure of arrays.
+// Pair-level arrays are [npair]; primitive-pair arrays are [nprim2][stride]
+// (primitive index major) so that lanes holding consecutive pairs read
+// consecutive addresses.  Pairs are sorted by Schwarz factor, descending.
+// ---------------------------------------------------------------------------
+struct PairSet {
+    int npair, nprim2, stride, pad_;
+    const int* sa;   // first shell (angular momentum la)
+    const int* sb;   // second shell
+    const int* fa;   // first function of sa
+    const int* fb;
+    const double* ABx;  // A - B
+    const double* ABy;
+    const double* ABz;
+    const double* Q;    // Schwarz factor of the pair (raw components)
+    const double* p;    // alpha + beta
+    const double* oo2p; // 1 / (2p)
+    const double* Px;   // (alpha A + beta B) / p
+    const double* Py;
+    const double* Pz;
+    const double* PAx;  // P - A
+    const double* PAy;
+    const double* PAz;
+    const double* K;    // c_a c_b exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p
+};
+
+// Work of one class (la lb|lc ld): one task per (a, 8 consecutive b, 8
+// consecutive d, a range of c); the wave loops over c.  Lane 8 i + j holds the quartet
+// (a b_i | c d_j).  Shells of each angular momentum are listed in index order
+// (shl_*), and ppos maps an oriented shell pair (higher l first; a >= b for
+// equal l) to its position in its pair class.
+struct TaskMap {
+    const int4* tasks;  // (a index, b chunk, d chunk, c_lo | c_hi << 16)
+    const int* ppos;    // [nshell * nshell]
+    const int* shl_a;
+    const int* shl_b;
+    const int* shl_c;
+    const int* shl_d;
+    int ntask, nshell;
+    int nsl_a, nsl_b, nsl_c, nsl_d;
+};
+
+// Sums over the 8 lanes sharing i (lanes 8i..8i+7) / sharing j.
+__device__ __forceinline__ double red_j(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+__device__ __forceinline__ double red_i(double v)
+{
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Densities and outputs of one build, interleaved [mu][nu][slot].
+struct Digest {
+    const double* X;  // [nbf][nbf][nX], scaled by component factors
+    double* J;        // [nbf][nbf][nJ] partial sums J'
+    double* K;        // [nbf][nbf][nK] partial sums K'
+    int nbf, nX, nJ, nK;
+    int jslot[CQ_MAX_MAT];
+    int kslot[CQ_MAX_MAT];
+    double skip;          // density-weighted Schwarz threshold (0: none)
+    const double* pmax;   // [nshell][nshell] max |X| per shell block
+    int nshell;
+    int pad_;
+};
+
+__device__ __forceinline__ double ld_x(const Digest& dg, int mu, int nu, int m)
+{
+    return dg.X[((long long)mu * dg.nbf + nu) * dg.nX + m];
+}
+__device__ __forceinline__ long long jidx(const Digest& dg, int mu, int nu, int s)
+{
+    return ((long long)mu * dg.nbf + nu) * dg.nJ + s;
+}
+__device__ __forceinline__ long long kidx(const Digest& dg, int mu, int nu, int s)
+{
+    return ((long long)mu * dg.nbf + nu) * dg.nK + s;
+}
+
+__device__ __forceinline__ void atomic_add(double* p, double v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double quartet_bound(const Digest& dg, double qab, double qcd, int a, int b, int c, int d)
+{
+    const double* pm = dg.pmax;
+    const int n = dg.nshell;
+    double m = fmax(fmax(pm[a * n + b], pm[c * n + d]), fmax(pm[a * n + c], pm[a * n + d]));
+    m = fmax(m, fmax(pm[b * n + c], pm[b * n + d]));
+    return qab * qcd * m;
+}

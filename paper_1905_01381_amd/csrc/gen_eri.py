@@ -1,0 +1,454 @@
+"""Generate the per-class electron-repulsion kernels (build step).
+
+For every class (la lb|lc ld) with la >= lb, lc >= ld and bra class >= ket
+class, this script emits straight-line HIP for the Head-Gordon-Pople scheme:
+
+1. Obara-Saika vertical recurrence (VRR) per primitive quartet, built on
+   the bra center A and the ket center C:
+     [e+1_i,0|f0]^(m) = PA_i [e0|f0]^(m) + WP_i [e0|f0]^(m+1)
+                        + e_i/(2p) ([e-1_i,0|f0]^(m) - rho/p [e-1_i,0|f0]^(m+1))
+                        + f_i/(2(p+q)) [e0|f-1_i,0]^(m+1)
+     [e0|f+1_i,0]^(m) = QC_i [e0|f0]^(m) + WQ_i [e0|f0]^(m+1)
+                        + f_i/(2q) ([e0|f-1_i,0]^(m) - rho/q [e0|f-1_i,0]^(m+1))
+                        + e_i/(2(p+q)) [e-1_i,0|f0]^(m+1)
+   from [00|00]^(m) = 2 pi^{5/2}/(p q sqrt(p+q)) K_ab K_cd F_m(rho |PQ|^2);
+2. contraction of the targets [e0|f0] (la <= |e| <= la+lb, lc <= |f| <= lc+ld)
+   over primitive quartets;
+3. horizontal recurrence (HRR) on the contracted integrals, bra then ket:
+     (a, b+1_i| = (a+1_i, b| + AB_i (a, b|,   |c, d+1_i) = |c+1_i, d) + CD_i |c, d);
+4. digestion into the Coulomb / exchange partial sums.
+
+The recurrences are the published Obara-Saika (1986) and Head-Gordon-Pople
+(1988) relations; every node of the recursion is generated on demand from the
+targets, so no unused intermediate is emitted.  Cartesian components are in
+lexicographic order (xx, xy, xz, yy, yz, zz).
+
+Usage: python gen_eri.py OUTDIR [--lmax 2]  (writes eri_<class>.hip and eri_registry.hpp)
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+DIRS = "xyz"
+
+
+def comps(l):
+    return [(i, j, l - i - j) for i in range(l, -1, -1) for j in range(l - i, -1, -1)]
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def tag(v):
+    return "".join(str(x) for x in v)
+
+
+def sub(v, i, k=1):
+    w = list(v)
+    w[i] -= k
+    return tuple(w)
+
+
+def add(v, i, k=1):
+    w = list(v)
+    w[i] += k
+    return tuple(w)
+
+
+class Emitter:
+    def __init__(self, ind="    "):
+        self.lines: list[str] = []
+        self.ind = ind
+
+    def __call__(self, s=""):
+        self.lines.append(self.ind + s if s else "")
+
+    def text(self):
+        return "\n".join(self.lines)
+
+
+# --------------------------------------------------------------------------
+# VRR
+# --------------------------------------------------------------------------
+class VRR:
+    """Demand-driven Obara-Saika VRR for one primitive quartet."""
+
+    def __init__(self, out: Emitter, L: int):
+        self.out = out
+        self.memo: dict = {}
+        self.L = L
+        self.count = 0
+
+    def name(self, e, f, m):
+        return f"r{tag(e)}_{tag(f)}_{m}"
+
+    def get(self, e, f, m):
+        if min(e) < 0 or min(f) < 0:
+            return None
+        key = (e, f, m)
+        if key in self.memo:
+            return self.memo[key]
+        nm = self.name(e, f, m)
+        if sum(e) == 0 and sum(f) == 0:
+            self.memo[key] = f"ss{m}"
+            return f"ss{m}"
+        terms = []
+        if sum(f) > 0:
+            i = next(k for k in range(3) if f[k] > 0)
+            f1 = sub(f, i)
+            a = self.get(e, f1, m)
+            b = self.get(e, f1, m + 1)
+            terms.append(f"QC{DIRS[i]} * {a}")
+            terms.append(f"WQ{DIRS[i]} * {b}")
+            if f1[i] > 0:
+                f2 = sub(f1, i)
+                c = self.get(e, f2, m)
+                d = self.get(e, f2, m + 1)
+                terms.append(f"{float(f1[i])} * (oo2q * {c} - rq2 * {d})")
+            if e[i] > 0:
+                g = self.get(sub(e, i), f1, m + 1)
+                terms.append(f"{float(e[i])} * oo2pq * {g}")
+        else:
+            i = next(k for k in range(3) if e[k] > 0)
+            e1 = sub(e, i)
+            a = self.get(e1, f, m)
+            b = self.get(e1, f, m + 1)
+            terms.append(f"PA{DIRS[i]} * {a}")
+            terms.append(f"WP{DIRS[i]} * {b}")
+            if e1[i] > 0:
+                e2 = sub(e1, i)
+                c = self.get(e2, f, m)
+                d = self.get(e2, f, m + 1)
+                terms.append(f"{float(e1[i])} * (oo2p * {c} - rp2 * {d})")
+        self.out(f"const double {nm} = " + " + ".join(terms) + ";")
+        self.count += 1
+        self.memo[key] = nm
+        return nm
+
+
+def class_name(la, lb, lc, ld):
+    s = "spdfg"
+    return f"{s[la]}{s[lb]}{s[lc]}{s[ld]}"
+
+
+def targets(la, lb, lc, ld):
+    es = [e for l in range(la, la + lb + 1) for e in comps(l)]
+    fs = [f for l in range(lc, lc + ld + 1) for f in comps(l)]
+    return es, fs
+
+
+def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
+    """Emit: accumulators, primitive loop (Boys + VRR + contraction), HRR.
+    Leaves v[NV] (raw contracted (ab|cd), layout [a][b][c][d]) defined."""
+    L = la + lb + lc + ld
+    es, fs = targets(la, lb, lc, ld)
+    eidx = {e: k for k, e in enumerate(es)}
+    fidx = {f: k for k, f in enumerate(fs)}
+    nE, nF = len(es), len(fs)
+    out(f"double acc[{nE * nF}];")
+    out(f"#pragma unroll")
+    out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = 0.0;")
+    out("for (int kp = 0; kp < bra.nprim2; ++kp) {")
+    out("  const double p = bra.p[kp * bra.stride + ib];")
+    out("  const double Kab = bra.K[kp * bra.stride + ib];")
+    out("  if (Kab == 0.0) continue;")
+    out("  const double oo2p = bra.oo2p[kp * bra.stride + ib];")
+    out("  const double Px = bra.Px[kp * bra.stride + ib], Py = bra.Py[kp * bra.stride + ib], Pz = bra.Pz[kp * bra.stride + ib];")
+    if la + lb > 0:
+        out("  const double PAx = bra.PAx[kp * bra.stride + ib], PAy = bra.PAy[kp * bra.stride + ib], PAz = bra.PAz[kp * bra.stride + ib];")
+    out("  for (int kq = 0; kq < ket.nprim2; ++kq) {")
+    out("    const double q = ket.p[kq * ket.stride + jk];")
+    out("    const double Kcd = ket.K[kq * ket.stride + jk];")
+    out("    const double oo2q = ket.oo2p[kq * ket.stride + jk];")
+    out("    const double Qx = ket.Px[kq * ket.stride + jk], Qy = ket.Py[kq * ket.stride + jk], Qz = ket.Pz[kq * ket.stride + jk];")
+    if lc + ld > 0:
+        out("    const double QCx = ket.PAx[kq * ket.stride + jk], QCy = ket.PAy[kq * ket.stride + jk], QCz = ket.PAz[kq * ket.stride + jk];")
+    out("    const double pq = p + q;")
+    out("    const double rs = rsqrt_f64(pq);")
+    out("    const double inv = rs * rs;")
+    out("    const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
+    out("    const double rho = p * q * inv;")
+    out("    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
+    out(f"    double F[{L + 1}];")
+    out(f"    boys_fp64<{L}>(T, boys_tab, F);")
+    out("    const double pref = Kab * Kcd * rs;")
+    for m in range(L + 1):
+        out(f"    const double ss{m} = pref * F[{m}];")
+    if L > 0:
+        out("    const double oo2pq = 0.5 * inv;")
+        if la + lb > 0:
+            out("    const double WPx = -q * inv * PQx, WPy = -q * inv * PQy, WPz = -q * inv * PQz;")
+            out("    const double rp2 = q * inv * oo2p;")
+        if lc + ld > 0:
+            out("    const double WQx = p * inv * PQx, WQy = p * inv * PQy, WQz = p * inv * PQz;")
+            out("    const double rq2 = p * inv * oo2q;")
+    inner = Emitter("    ")
+    vrr = VRR(inner, L)
+    for e in es:
+        for f in fs:
+            vrr.get(e, f, 0)
+    out.lines.extend(inner.lines)
+    for e in es:
+        for f in fs:
+            out(f"    acc[{eidx[e] * nF + fidx[f]}] += {vrr.memo[(e, f, 0)]};")
+    out("  }")
+    out("}")
+    # HRR bra: (a,b|f] for every ket target f
+    A_, B_, C_, D_ = comps(la), comps(lb), comps(lc), comps(ld)
+    hb: dict = {}
+
+    def bra(a, b, f):
+        key = (a, b, f)
+        if key in hb:
+            return hb[key]
+        if sum(b) == 0:
+            nm = f"acc[{eidx[a] * nF + fidx[f]}]"
+            hb[key] = nm
+            return nm
+        i = next(k for k in range(3) if b[k] > 0)
+        x = bra(add(a, i), sub(b, i), f)
+        y = bra(a, sub(b, i), f)
+        nm = f"hb{tag(a)}_{tag(b)}_{tag(f)}"
+        out(f"const double {nm} = {x} + AB{DIRS[i]} * {y};")
+        hb[key] = nm
+        return nm
+
+    hk: dict = {}
+
+    def ket(a, b, c, d):
+        key = (a, b, c, d)
+        if key in hk:
+            return hk[key]
+        if sum(d) == 0:
+            nm = bra(a, b, c)
+            hk[key] = nm
+            return nm
+        i = next(k for k in range(3) if d[k] > 0)
+        x = ket(a, b, add(c, i), sub(d, i))
+        y = ket(a, b, c, sub(d, i))
+        nm = f"hk{tag(a)}_{tag(b)}_{tag(c)}_{tag(d)}"
+        out(f"const double {nm} = {x} + CD{DIRS[i]} * {y};")
+        hk[key] = nm
+        return nm
+
+    nv = len(A_) * len(B_) * len(C_) * len(D_)
+    out(f"double v[{nv}];")
+    n = 0
+    for a in A_:
+        for b in B_:
+            for c in C_:
+                for d in D_:
+                    out(f"v[{n}] = {ket(a, b, c, d)};")
+                    n += 1
+    return nv, vrr.count
+
+
+def emit_digest(out: Emitter, la, lb, lc, ld):
+    """Digestion of one step of a task: the wave holds the 64 quartets
+    (a b_i | c d_j), lane = 8 i + j, with v[] already weighted by the
+    permutational degeneracy.  Partial sums are reduced across the lanes
+    that share a destination before the single atomic flush:
+      J'_ab += 2 v X_cd   (same b: reduce over j)
+      J'_cd += 2 v X_ab   (same d: reduce over i)
+      K'_ac += v X_bd     (one destination per wave: reduce over all lanes)
+      K'_ad += v X_bc     (reduce over i)
+      K'_bc += v X_ad     (reduce over j)
+      K'_bd += v X_ac     (one destination per lane)."""
+    na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
+
+    def V(i, j, k, l):
+        return f"v[{((i * nb + j) * nc + k) * nd + l}]"
+
+    out("for (int m = 0; m < dg.nX; ++m) {")
+    out("  const int js = dg.jslot[m], ks = dg.kslot[m];")
+    out("  if (js >= 0) {")
+    for k in range(nc):
+        for l in range(nd):
+            out(f"    const double xcd{k}{l} = ld_x(dg, fc + {k}, fd + {l}, m);")
+    for i in range(na):
+        for j in range(nb):
+            out(f"    const double xab{i}{j} = ld_x(dg, fa + {i}, fb + {j}, m);")
+    for i in range(na):
+        for j in range(nb):
+            s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
+            out(f"    {{ const double s = red_j(2.0 * ({s})); if (dj == 0 && rowv) atomic_add(dg.J + jidx(dg, fa + {i}, fb + {j}, js), s); }}")
+    for k in range(nc):
+        for l in range(nd):
+            s = " + ".join(f"{V(i, j, k, l)} * xab{i}{j}" for i in range(na) for j in range(nb))
+            out(f"    {{ const double s = red_i(2.0 * ({s})); if (bi == 0 && colv) atomic_add(dg.J + jidx(dg, fc + {k}, fd + {l}, js), s); }}")
+    out("  }")
+    out("  if (ks >= 0) {")
+    for j in range(nb):
+        for l in range(nd):
+            out(f"    const double xbd{j}{l} = ld_x(dg, fb + {j}, fd + {l}, m);")
+    for j in range(nb):
+        for k in range(nc):
+            out(f"    const double xbc{j}{k} = ld_x(dg, fb + {j}, fc + {k}, m);")
+    for i in range(na):
+        for l in range(nd):
+            out(f"    const double xad{i}{l} = ld_x(dg, fa + {i}, fd + {l}, m);")
+    for i in range(na):
+        for k in range(nc):
+            out(f"    const double xac{i}{k} = ld_x(dg, fa + {i}, fc + {k}, m);")
+    for i in range(na):
+        for k in range(nc):
+            s = " + ".join(f"{V(i, j, k, l)} * xbd{j}{l}" for j in range(nb) for l in range(nd))
+            out(f"    {{ const double s = red_i(red_j({s})); if (lane == 0) atomic_add(dg.K + kidx(dg, fa + {i}, fc + {k}, ks), s); }}")
+    for i in range(na):
+        for l in range(nd):
+            s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
+            out(f"    {{ const double s = red_i({s}); if (bi == 0 && colv) atomic_add(dg.K + kidx(dg, fa + {i}, fd + {l}, ks), s); }}")
+    for j in range(nb):
+        for k in range(nc):
+            s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
+            out(f"    {{ const double s = red_j({s}); if (dj == 0 && rowv) atomic_add(dg.K + kidx(dg, fb + {j}, fc + {k}, ks), s); }}")
+    for j in range(nb):
+        for l in range(nd):
+            s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
+            out(f"    if (active) atomic_add(dg.K + kidx(dg, fb + {j}, fd + {l}, ks), {s});")
+    out("  }")
+    out("}")
+
+
+def all_classes(lmax):
+    pcls = [(a, b) for a in range(lmax + 1) for b in range(a + 1)]
+    out = []
+    for i, P in enumerate(pcls):
+        for Q in pcls[: i + 1]:
+            out.append((P[0], P[1], Q[0], Q[1]))
+    return pcls, out
+
+
+HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
+// Head-Gordon-Pople electron-repulsion kernels (one thread per contracted
+// shell quartet) with Coulomb/exchange digestion."""
+
+
+def gen(lmax: int) -> dict:
+    pcls, classes = all_classes(lmax)
+    files = {}
+    stats = []
+    for (la, lb, lc, ld) in classes:
+        o = Emitter("")
+        o(HEADER)
+        o('#include "eri_common.hpp"')
+        o("")
+        cn = class_name(la, lb, lc, ld)
+        L = la + lb + lc + ld
+        # J/K kernel
+        body = Emitter("    ")
+        nv, nvrr = emit_eri_body(body, la, lb, lc, ld)
+        dig = Emitter("    ")
+        emit_digest(dig, la, lb, lc, ld)
+        stats.append((cn, nv, nvrr))
+        o(f"// ({cn}) L={L}: {nv} integrals, {nvrr} VRR nodes per primitive quartet")
+        same_ab = int(la == lb)
+        same_cd = int(lc == ld)
+        same_cls = int((la, lb) == (lc, ld))
+        o(f"__global__ __launch_bounds__(64) void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab)")
+        o("{")
+        o("  const int lane = threadIdx.x;")
+        o("  const int bi = lane >> 3, dj = lane & 7;")
+        o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
+        o("    const int4 tk = tm.tasks[task];")
+        o("    const int a_idx = tk.x, b_idx = tk.y * 8 + bi, d_idx = tk.z * 8 + dj;")
+        o(f"    const bool rowv = b_idx < ({'a_idx + 1' if same_ab else 'tm.nsl_b'});")
+        o("    const bool dval = d_idx < tm.nsl_d;")
+        o("    const int a = tm.shl_a[a_idx];")
+        o("    const int b = tm.shl_b[rowv ? b_idx : tk.y * 8];")
+        o("    const int d = tm.shl_d[dval ? d_idx : tk.z * 8];")
+        o("    const int ib = tm.ppos[a * tm.nshell + b];")
+        o("    const int fa = bra.fa[ib], fb = bra.fb[ib];")
+        if lb > 0:
+            o("    const double ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
+        o(f"    const int c_lo = tk.w & 0xffff;")
+        o(f"    const int c_hi = tk.w >> 16;")
+        o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
+        o("      const int c = tm.shl_c[c_idx];")
+        o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
+        o("      bool active = rowv && colv;")
+        if same_cls:
+            o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
+        o(f"      const int jk = tm.ppos[c * tm.nshell + (colv ? d : {'c' if same_cd else 'd'})];")
+        o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
+        o("      if (dg.skip > 0.0 && active) active = quartet_bound(dg, bra.Q[ib], ket.Q[jk], a, b, c, d) >= dg.skip;")
+        o("      if (!__any(active)) continue;")
+        if ld > 0:
+            o("      const double CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
+        body.ind = "      "
+        body.lines = ["  " + x if x else x for x in body.lines]
+        o(body.text())
+        o("      double deg = active ? 1.0 : 0.0;")
+        if same_ab:
+            o("      if (a == b) deg *= 0.5;")
+        if same_cd:
+            o("      if (c == d) deg *= 0.5;")
+        if same_cls:
+            o("      if (a == c && b == d) deg *= 0.5;")
+        o(f"      #pragma unroll")
+        o(f"      for (int t = 0; t < {nv}; ++t) v[t] *= deg;")
+        dig.lines = ["  " + x if x else x for x in dig.lines]
+        o(dig.text())
+        o("    }")
+        o("  }")
+        o("}")
+        o("")
+        # block kernel (tests and Schwarz): quartet list -> raw blocks
+        body2 = Emitter("  ")
+        emit_eri_body(body2, la, lb, lc, ld)
+        o(f"__global__ __launch_bounds__(64) void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab)")
+        o("{")
+        o("  const int t = blockIdx.x * blockDim.x + threadIdx.x;")
+        o("  if (t >= nq) return;")
+        o("  const int ib = qlist[2 * t], jk = qlist[2 * t + 1];")
+        if lb > 0:
+            o("  const double ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
+        if ld > 0:
+            o("  const double CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
+        o(body2.text())
+        o(f"  #pragma unroll")
+        o(f"  for (int u = 0; u < {nv}; ++u) out[(long long)t * {nv} + u] = v[u];")
+        o("}")
+        files[f"eri_{cn}.hip"] = o.text() + "\n"
+    o = Emitter("")
+    o(HEADER)
+    o("#pragma once")
+    o('#include "eri_common.hpp"')
+    for (la, lb, lc, ld) in classes:
+        cn = class_name(la, lb, lc, ld)
+        o(f"__global__ void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
+        o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
+    # dispatch tables
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; void (*jk)(PairSet, PairSet, TaskMap, Digest, const double*); void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o(f"static const int kNumEriClasses = {len(classes)};")
+    o("static const EriClassEntry kEriClasses[] = {")
+    for (la, lb, lc, ld) in classes:
+        cn = class_name(la, lb, lc, ld)
+        nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, eri_jk_{cn}, eri_block_{cn}}},")
+    o("};")
+    for cn, nv, nvrr in stats:
+        print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)
+    files["eri_registry.hpp"] = o.text() + "\n"
+    return files
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("outdir")
+    ap.add_argument("--lmax", type=int, default=2)
+    a = ap.parse_args()
+    os.makedirs(a.outdir, exist_ok=True)
+    for name, src in gen(a.lmax).items():
+        path = os.path.join(a.outdir, name)
+        old = open(path).read() if os.path.exists(path) else None
+        if old != src:
+            with open(path, "w") as f:
+                f.write(src)
+
+
+if __name__ == "__main__":
+    main()
