@@ -37,8 +37,22 @@ def generate(verbose: bool = False) -> list[str]:
     return sorted(glob.glob(os.path.join(GEN, "eri_*.hip")))
 
 
-def _compile(src: str, extra: list[str]) -> tuple[str, str]:
+def _headers() -> list[str]:
+    return (glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(GEN, "*.hpp"))
+            + [os.path.join(ROOT, "include", "cq.h"), __file__])
+
+
+def _fresh(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(x) <= t for x in [src, *_headers()])
+
+
+def _compile(src: str, extra: list[str], incremental: bool = False) -> tuple[str, str]:
     obj = os.path.join(OBJ, os.path.basename(src).replace(".hip", ".o"))
+    if incremental and _fresh(src, obj):
+        return obj, ""
     tmp = obj + f".tmp{os.getpid()}"
     cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", GEN,
            "-c", src, "-o", tmp]
@@ -49,7 +63,10 @@ def _compile(src: str, extra: list[str]) -> tuple[str, str]:
     return obj, r.stderr
 
 
-def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None) -> str:
+def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None,
+          incremental: bool = False) -> str:
+    """Compile every translation unit (always, unless ``incremental``, which
+    skips objects newer than their sources and headers) and link libcq.so."""
     t0 = time.time()
     extra = extra or []
     os.makedirs(OBJ, exist_ok=True)
@@ -57,7 +74,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     objs, logs = [], []
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for obj, log in ex.map(lambda s: _compile(s, extra), srcs):
+        for obj, log in ex.map(lambda s: _compile(s, extra, incremental), srcs):
             objs.append(obj)
             logs.append(log)
     tmp = LIB + f".tmp{os.getpid()}"
@@ -73,4 +90,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=sys.argv[1:])
+    args = sys.argv[1:]
+    inc = "--incremental" in args
+    args = [a for a in args if a != "--incremental"]
+    build(verbose=True, extra=args, incremental=inc)

@@ -125,7 +125,8 @@ struct Digest {
     double skip;          // density-weighted Schwarz threshold (0: none)
     const double* pmax;   // [nshell][nshell] max |X| per shell block
     int nshell;
-    int pad_;
+    int stage_blocks;     // waves that own a stage region (grid limit of staged classes)
+    double* stage;        // per-wave private stage, [stage_blocks][class stage size][64]
 };
 
 __device__ __forceinline__ double ld_x(const Digest& dg, int mu, int nu, int m)
@@ -152,6 +153,31 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Per-wave stage of the staged kernels, addressed through a buffer resource:
+// element i of lane l lives at byte 512 i + 8 l of the wave's region, so one
+// VGPR (8 l) and a uniform scalar offset (512 i) address every element and
+// no per-element address registers are kept live.
+typedef __amdgpu_buffer_rsrc_t stage_rsrc;
+typedef unsigned int stage_u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ stage_rsrc stage_make(double* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double stage_load(stage_rsrc r, int voff, int i)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, i * 512, 0));
+}
+__device__ __forceinline__ void stage_store(stage_rsrc r, int voff, int i, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(stage_u32x2, x), r, voff, i * 512, 0);
+}
+
+// Compiler-only barrier between the phases of the staged kernels: values
+// written to the per-wave stage are re-read from memory instead of being
+// forwarded in registers (which would defeat the staging).
+__device__ __forceinline__ void stage_fence() { __asm__ volatile("" ::: "memory"); }
 
 __device__ __forceinline__ double quartet_bound(const Digest& dg, double qab, double qcd, int a, int b, int c, int d)
 {

@@ -140,17 +140,11 @@ def targets(la, lb, lc, ld):
     return es, fs
 
 
-def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
-    """Emit: accumulators, primitive loop (Boys + VRR + contraction), HRR.
-    Leaves v[NV] (raw contracted (ab|cd), layout [a][b][c][d]) defined."""
+def emit_prim_header(out: Emitter, la, lb, lc, ld):
+    """Open the primitive-quartet loops and emit the per-primitive setup:
+    Gaussian-product data, the Boys function F_0..F_L and the VRR
+    coefficients (the loops are closed by the caller)."""
     L = la + lb + lc + ld
-    es, fs = targets(la, lb, lc, ld)
-    eidx = {e: k for k, e in enumerate(es)}
-    fidx = {f: k for k, f in enumerate(fs)}
-    nE, nF = len(es), len(fs)
-    out(f"double acc[{nE * nF}];")
-    out(f"#pragma unroll")
-    out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = 0.0;")
     out("for (int kp = 0; kp < bra.nprim2; ++kp) {")
     out("  const double p = bra.p[kp * bra.stride + ib];")
     out("  const double Kab = bra.K[kp * bra.stride + ib];")
@@ -185,6 +179,20 @@ def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
         if lc + ld > 0:
             out("    const double WQx = p * inv * PQx, WQy = p * inv * PQy, WQz = p * inv * PQz;")
             out("    const double rq2 = p * inv * oo2q;")
+
+
+def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
+    """Emit: accumulators, primitive loop (Boys + VRR + contraction), HRR.
+    Leaves v[NV] (raw contracted (ab|cd), layout [a][b][c][d]) defined."""
+    L = la + lb + lc + ld
+    es, fs = targets(la, lb, lc, ld)
+    eidx = {e: k for k, e in enumerate(es)}
+    fidx = {f: k for k, f in enumerate(fs)}
+    nE, nF = len(es), len(fs)
+    out(f"double acc[{nE * nF}];")
+    out(f"#pragma unroll")
+    out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = 0.0;")
+    emit_prim_header(out, la, lb, lc, ld)
     inner = Emitter("    ")
     vrr = VRR(inner, L)
     for e in es:
@@ -313,6 +321,205 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
     out("}")
 
 
+
+# --------------------------------------------------------------------------
+# Staged variant for high angular momentum: the contracted intermediates do
+# not fit one lane's registers, so the VRR runs in passes over subsets of
+# <= STAGE_CAP targets (each pass re-runs the primitive loop for its own
+# subset), and the contracted [e0|f0], the bra-transferred (ab|f] and the
+# final (ab|cd) go through a per-wave global stage laid out [index][lane]
+# (coalesced, private to the wave).
+# --------------------------------------------------------------------------
+STAGE_CAP = 48
+
+
+def is_staged(la, lb, lc, ld):
+    es, fs = targets(la, lb, lc, ld)
+    nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+    return len(es) * len(fs) > 96 or nv > 150
+
+
+def stage_subsets(la, lb, lc, ld, cap=STAGE_CAP):
+    out = []
+    for le in range(la, la + lb + 1):
+        for lf in range(lc, lc + ld + 1):
+            E, F = comps(le), comps(lf)
+            per = max(1, cap // len(F))
+            for k in range(0, len(E), per):
+                out.append([(e, f) for e in E[k:k + per] for f in F])
+    return out
+
+
+def stage_layout(la, lb, lc, ld):
+    es, fs = targets(la, lb, lc, ld)
+    nE, nF = len(es), len(fs)
+    nab = ncart(la) * ncart(lb)
+    ncd = ncart(lc) * ncart(ld)
+    G0, HB0 = 0, nE * nF
+    V0 = HB0 + nab * nF
+    return G0, HB0, V0, V0 + nab * ncd
+
+
+def emit_staged_eri(out: Emitter, la, lb, lc, ld):
+    L = la + lb + lc + ld
+    es, fs = targets(la, lb, lc, ld)
+    eidx = {e: k for k, e in enumerate(es)}
+    fidx = {f: k for k, f in enumerate(fs)}
+    nF = len(fs)
+    G0, HB0, V0, _ = stage_layout(la, lb, lc, ld)
+    nodes = 0
+    for sub_ in stage_subsets(la, lb, lc, ld):
+        out("{")
+        out(f"  double acc[{len(sub_)}];")
+        out(f"  #pragma unroll")
+        out(f"  for (int t = 0; t < {len(sub_)}; ++t) acc[t] = 0.0;")
+        hdr = Emitter(out.ind + "  ")
+        emit_prim_header(hdr, la, lb, lc, ld)
+        out.lines.extend(hdr.lines)
+        inner = Emitter(out.ind + "      ")
+        vrr = VRR(inner, L)
+        for (e, f) in sub_:
+            vrr.get(e, f, 0)
+        nodes += vrr.count
+        out.lines.extend(inner.lines)
+        for k, (e, f) in enumerate(sub_):
+            out(f"      acc[{k}] += {vrr.memo[(e, f, 0)]};")
+        out("    }")
+        out("  }")
+        for k, (e, f) in enumerate(sub_):
+            out(f"  STS({G0 + eidx[e] * nF + fidx[f]}, acc[{k}]);")
+        out("}")
+        out("stage_fence();")
+    A_, B_, C_, D_ = comps(la), comps(lb), comps(lc), comps(ld)
+    # bra transfer, one ket target f at a time
+    for f in fs:
+        out("{")
+        needed = set()
+
+        def collect(a, b):
+            if sum(b) == 0:
+                needed.add(a)
+                return
+            i = next(k for k in range(3) if b[k] > 0)
+            collect(add(a, i), sub(b, i))
+            collect(a, sub(b, i))
+
+        for a in A_:
+            for b in B_:
+                collect(a, b)
+        for e in sorted(needed, key=lambda x: eidx[x]):
+            out(f"  const double g{tag(e)} = STL({G0 + eidx[e] * nF + fidx[f]});")
+        memo = {}
+
+        def bra(a, b):
+            if (a, b) in memo:
+                return memo[(a, b)]
+            if sum(b) == 0:
+                memo[(a, b)] = f"g{tag(a)}"
+                return memo[(a, b)]
+            i = next(k for k in range(3) if b[k] > 0)
+            x = bra(add(a, i), sub(b, i))
+            y = bra(a, sub(b, i))
+            nm = f"h{tag(a)}_{tag(b)}"
+            out(f"  const double {nm} = {x} + AB{DIRS[i]} * {y};")
+            memo[(a, b)] = nm
+            return nm
+
+        for ia, a in enumerate(A_):
+            for ib_, b in enumerate(B_):
+                out(f"  STS({HB0 + (ia * len(B_) + ib_) * nF + fidx[f]}, {bra(a, b)});")
+        out("}")
+    out("stage_fence();")
+    # ket transfer, one bra function pair at a time; weight by degeneracy
+    ncd = len(C_) * len(D_)
+    for ab in range(len(A_) * len(B_)):
+        out("{")
+        needed = set()
+
+        def collectk(c, d):
+            if sum(d) == 0:
+                needed.add(c)
+                return
+            i = next(k for k in range(3) if d[k] > 0)
+            collectk(add(c, i), sub(d, i))
+            collectk(c, sub(d, i))
+
+        for c in C_:
+            for d in D_:
+                collectk(c, d)
+        for f in sorted(needed, key=lambda x: fidx[x]):
+            out(f"  const double q{tag(f)} = STL({HB0 + ab * nF + fidx[f]});")
+        memo = {}
+
+        def ket(c, d):
+            if (c, d) in memo:
+                return memo[(c, d)]
+            if sum(d) == 0:
+                memo[(c, d)] = f"q{tag(c)}"
+                return memo[(c, d)]
+            i = next(k for k in range(3) if d[k] > 0)
+            x = ket(add(c, i), sub(d, i))
+            y = ket(c, sub(d, i))
+            nm = f"k{tag(c)}_{tag(d)}"
+            out(f"  const double {nm} = {x} + CD{DIRS[i]} * {y};")
+            memo[(c, d)] = nm
+            return nm
+
+        for ic, c in enumerate(C_):
+            for id_, d in enumerate(D_):
+                out(f"  STS({V0 + ab * ncd + ic * len(D_) + id_}, deg * {ket(c, d)});")
+        out("}")
+    out("stage_fence();")
+    return nodes
+
+
+def emit_staged_digest(out: Emitter, la, lb, lc, ld):
+    """Digestion reading (ab|cd) from the stage: for every output element the
+    contributing integrals are loaded once, then the loop over densities
+    reuses them (lane reductions and flush as in emit_digest)."""
+    na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
+    _, _, V0, _ = stage_layout(la, lb, lc, ld)
+
+    def Vi(i, j, k, l):
+        return V0 + ((i * nb + j) * nc + k) * nd + l
+
+    # (name, output index pairs, summed index pairs, V index fn, X row/col, dest, reduction, guard, scale, slot)
+    specs = [
+        ("J_ab", [(i, j) for i in range(na) for j in range(nb)], [(k, l) for k in range(nc) for l in range(nd)],
+         lambda o, s: Vi(o[0], o[1], s[0], s[1]), ("fc", "fd"), ("J", "fa", "fb", "js"), "red_j", "dj == 0 && rowv", "2.0 * "),
+        ("J_cd", [(k, l) for k in range(nc) for l in range(nd)], [(i, j) for i in range(na) for j in range(nb)],
+         lambda o, s: Vi(s[0], s[1], o[0], o[1]), ("fa", "fb"), ("J", "fc", "fd", "js"), "red_i", "bi == 0 && colv", "2.0 * "),
+        ("K_ac", [(i, k) for i in range(na) for k in range(nc)], [(j, l) for j in range(nb) for l in range(nd)],
+         lambda o, s: Vi(o[0], s[0], o[1], s[1]), ("fb", "fd"), ("K", "fa", "fc", "ks"), "red_all", "lane == 0", ""),
+        ("K_ad", [(i, l) for i in range(na) for l in range(nd)], [(j, k) for j in range(nb) for k in range(nc)],
+         lambda o, s: Vi(o[0], s[0], s[1], o[1]), ("fb", "fc"), ("K", "fa", "fd", "ks"), "red_i", "bi == 0 && colv", ""),
+        ("K_bc", [(j, k) for j in range(nb) for k in range(nc)], [(i, l) for i in range(na) for l in range(nd)],
+         lambda o, s: Vi(s[0], o[0], o[1], s[1]), ("fa", "fd"), ("K", "fb", "fc", "ks"), "red_j", "dj == 0 && rowv", ""),
+        ("K_bd", [(j, l) for j in range(nb) for l in range(nd)], [(i, k) for i in range(na) for k in range(nc)],
+         lambda o, s: Vi(s[0], o[0], s[1], o[1]), ("fa", "fc"), ("K", "fb", "fd", "ks"), "none", "active", ""),
+    ]
+    for (name, outs, sums, vfn, (xr, xc), (arr, dr, dc, slot), red, guard, scale) in specs:
+        isJ = arr == "J"
+        for o in outs:
+            out("{")
+            for t, sidx in enumerate(sums):
+                out(f"  const double w{t} = STL({vfn(o, sidx)});")
+            out("  for (int m = 0; m < dg.nX; ++m) {")
+            out(f"    const int {slot} = dg.{'jslot' if isJ else 'kslot'}[m];")
+            out(f"    if ({slot} < 0) continue;")
+            terms = " + ".join(f"w{t} * ld_x(dg, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)" for t, sidx in enumerate(sums))
+            val = f"{scale}({terms})"
+            if red == "red_all":
+                val = f"red_i(red_j({val}))"
+            elif red != "none":
+                val = f"{red}({val})"
+            idxf = "jidx" if isJ else "kidx"
+            out(f"    const double s = {val};")
+            out(f"    if ({guard}) atomic_add(dg.{arr} + {idxf}(dg, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s);")
+            out("  }")
+            out("}")
+
+
 def all_classes(lmax):
     pcls = [(a, b) for a in range(lmax + 1) for b in range(a + 1)]
     out = []
@@ -331,6 +538,7 @@ def gen(lmax: int) -> dict:
     pcls, classes = all_classes(lmax)
     files = {}
     stats = []
+    stage_sizes = {}
     for (la, lb, lc, ld) in classes:
         o = Emitter("")
         o(HEADER)
@@ -339,10 +547,19 @@ def gen(lmax: int) -> dict:
         cn = class_name(la, lb, lc, ld)
         L = la + lb + lc + ld
         # J/K kernel
+        staged = is_staged(la, lb, lc, ld)
         body = Emitter("    ")
-        nv, nvrr = emit_eri_body(body, la, lb, lc, ld)
         dig = Emitter("    ")
-        emit_digest(dig, la, lb, lc, ld)
+        nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+        if staged:
+            nvrr = emit_staged_eri(body, la, lb, lc, ld)
+            emit_staged_digest(dig, la, lb, lc, ld)
+            stage_n = stage_layout(la, lb, lc, ld)[3]
+        else:
+            nv, nvrr = emit_eri_body(body, la, lb, lc, ld)
+            emit_digest(dig, la, lb, lc, ld)
+            stage_n = 0
+        stage_sizes[(la, lb, lc, ld)] = stage_n
         stats.append((cn, nv, nvrr))
         o(f"// ({cn}) L={L}: {nv} integrals, {nvrr} VRR nodes per primitive quartet")
         same_ab = int(la == lb)
@@ -352,6 +569,11 @@ def gen(lmax: int) -> dict:
         o("{")
         o("  const int lane = threadIdx.x;")
         o("  const int bi = lane >> 3, dj = lane & 7;")
+        if staged:
+            o(f"  const stage_rsrc srs = stage_make(dg.stage + (size_t)blockIdx.x * ({stage_n} * 64), {stage_n} * 512);")
+            o("  const int svo = lane * 8;")
+            o("#define STL(i) stage_load(srs, svo, (i))")
+            o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
         o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
         o("    const int4 tk = tm.tasks[task];")
         o("    const int a_idx = tk.x, b_idx = tk.y * 8 + bi, d_idx = tk.z * 8 + dj;")
@@ -380,7 +602,6 @@ def gen(lmax: int) -> dict:
             o("      const double CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
         body.ind = "      "
         body.lines = ["  " + x if x else x for x in body.lines]
-        o(body.text())
         o("      double deg = active ? 1.0 : 0.0;")
         if same_ab:
             o("      if (a == b) deg *= 0.5;")
@@ -388,12 +609,17 @@ def gen(lmax: int) -> dict:
             o("      if (c == d) deg *= 0.5;")
         if same_cls:
             o("      if (a == c && b == d) deg *= 0.5;")
-        o(f"      #pragma unroll")
-        o(f"      for (int t = 0; t < {nv}; ++t) v[t] *= deg;")
+        o(body.text())
+        if not staged:
+            o(f"      #pragma unroll")
+            o(f"      for (int t = 0; t < {nv}; ++t) v[t] *= deg;")
         dig.lines = ["  " + x if x else x for x in dig.lines]
         o(dig.text())
         o("    }")
         o("  }")
+        if staged:
+            o("#undef STL")
+            o("#undef STS")
         o("}")
         o("")
         # block kernel (tests and Schwarz): quartet list -> raw blocks
@@ -422,13 +648,13 @@ def gen(lmax: int) -> dict:
         o(f"__global__ void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
         o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
     # dispatch tables
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; void (*jk)(PairSet, PairSet, TaskMap, Digest, const double*); void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; void (*jk)(PairSet, PairSet, TaskMap, Digest, const double*); void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, eri_jk_{cn}, eri_block_{cn}}},")
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, eri_jk_{cn}, eri_block_{cn}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)
