@@ -55,8 +55,12 @@ typedef struct cq_basis_s* cq_basis;
  *               quartet touches, maximized over all densities; the paper's
  *               LinK-like screening, "Reference Wave Functions") is below
  *               this value are not evaluated.  0 = no screening (exact).
- *   fp32_below: in mode 1, quartet batches whose bound is below this value
- *               are evaluated in FP32 (with compensated accumulation).
+ *   fp32_below: in mode 1, a batch of 64 quartets (one wave step: one bra
+ *               shell a, eight b, one c, eight d) whose largest bound is below
+ *               this value is evaluated in FP32: FP32 recurrences with
+ *               compensated (Kahan) accumulation over primitives, FP32 partial
+ *               sums folded into the FP64 J and K; the Boys function for
+ *               T >= 36 or order >= 6 stays FP64.  Other batches run in FP64.
  *   mode:       0 = FP64 throughout; 1 = precision-routed.
  *   flags:      CQ_ACCUMULATE adds into J/K instead of overwriting them. */
 typedef struct {
@@ -152,6 +156,11 @@ cq_status cq_one_electron(cq_basis b, int kind, int dir, const double* origin, i
  * build (bra pair >= ket pair; la>=lb, lc>=ld).  For entry k < maxn:
  * cls[4k..4k+3] = (la, lb, lc, ld), count[k]; *n = number of classes. */
 cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, int* n);
+
+/* Quartet counts of the most recent cq_jk_build / cq_fock2e_2c on this
+ * basis, written to HOST out3: [0] evaluated in FP64, [1] evaluated in FP32
+ * (precision-routed mode), [2] removed by screening.  Synchronizes `stream`. */
+cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t stream);
 
 /* Per-class launch timing with HIP events recorded on the launch stream
  * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.

@@ -60,10 +60,11 @@ def lib():
         llp = ctypes.POINTER(ctypes.c_longlong)
         L.cq_quartet_counts.argtypes = [vp, i, ip, llp, ip]
         L.cq_profile.argtypes = [vp, i]
+        L.cq_build_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong), vp]
         L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
         for name in ("cq_basis_create", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
                      "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile",
-                     "cq_profile_read"):
+                     "cq_profile_read", "cq_build_stats"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -206,6 +207,12 @@ class Basis:
         cnt = (ctypes.c_longlong * 64)()
         _check(lib().cq_quartet_counts(self.h, 64, cls, cnt, ctypes.byref(n)))
         return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
+
+    def build_stats(self, stream=None) -> dict:
+        """Quartets of the last build: evaluated in FP64 / FP32, skipped."""
+        out = (ctypes.c_ulonglong * 3)()
+        _check(lib().cq_build_stats(self.h, out, _stream(stream)))
+        return {"fp64": int(out[0]), "fp32": int(out[1]), "skipped": int(out[2])}
 
     def profile(self, enable: bool = True, reset: bool = False):
         _check(lib().cq_profile(self.h, 2 if (enable and reset) else int(enable)))

@@ -21,6 +21,7 @@
 #define BOYS_LMAX 16
 
 __device__ __forceinline__ double rsqrt_f64(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsqrt_f32(float x) { return rsqrtf(x); }
 
 template <int L>
 __device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ tab, double* F)
@@ -53,6 +54,52 @@ __device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ t
             for (int m = 0; m < L; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * h;
         }
     }
+}
+
+// FP32 Boys function for the precision-routed path.  The table of FP32
+// Chebyshev coefficients follows the FP64 table in the same allocation.
+// Large arguments (T >= BOYS_TC) and high orders (L >= 6) are evaluated in
+// FP64 and rounded, so only the low-order, small-argument part runs in FP32.
+#define BOYS_TAB_DOUBLES ((BOYS_LMAX + 1) * BOYS_NINT * BOYS_NC)
+
+template <int L>
+__device__ __forceinline__ void boys_fp32(float T, const double* __restrict__ tab, float* F)
+{
+    if (L >= 6 || !(T < (float)BOYS_TC)) {
+        double Fd[L + 1];
+        boys_fp64<L>((double)T, tab, Fd);
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] = (float)Fd[m];
+        return;
+    }
+    const float* tf = (const float*)(tab + BOYS_TAB_DOUBLES);
+    int k = (int)(T * (1.0f / (float)BOYS_H));
+    k = k < 0 ? 0 : (k > BOYS_NINT - 1 ? BOYS_NINT - 1 : k);
+    const float x = (T - k * (float)BOYS_H) * (2.0f / (float)BOYS_H) - 1.0f;
+    const float* c = tf + ((size_t)L * BOYS_NINT + k) * BOYS_NC;
+    float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+    for (int j = BOYS_NC - 1; j >= 1; --j) {
+        const float b0 = fmaf(2.0f * x, b1, c[j] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    F[L] = fmaf(x, b1, c[0] - b2);
+    if (L > 0) {
+        const float e = expf(-T);
+        const float t2 = 2.0f * T;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) F[m] = fmaf(t2, F[m + 1], e) * (1.0f / (2 * m + 1));
+    }
+}
+
+// Compensated (Kahan) FP32 accumulation: s + c carries the running sum.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +174,10 @@ struct Digest {
     int nshell;
     int stage_blocks;     // waves that own a stage region (grid limit of staged classes)
     double* stage;        // per-wave private stage, [stage_blocks][class stage size][64]
+    int mode;             // 0: FP64 everywhere; 1: precision-routed
+    int pad2_;
+    double fp32_below;    // routed mode: a wave step whose largest bound is below this runs in FP32
+    unsigned long long* counts;  // [3]: quartets evaluated in FP64, in FP32, skipped by screening
 };
 
 __device__ __forceinline__ double ld_x(const Digest& dg, int mu, int nu, int m)
@@ -145,6 +196,46 @@ __device__ __forceinline__ long long kidx(const Digest& dg, int mu, int nu, int 
 __device__ __forceinline__ void atomic_add(double* p, double v)
 {
     unsafeAtomicAdd(p, v);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float red_jf(float v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+__device__ __forceinline__ float red_if(float v)
+{
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Per wave step, one atomic per wave: the FP64 kernel counts the quartets it
+// evaluates (slot 0) and those removed by screening (slot 2); the FP32
+// kernel counts the quartets it evaluates (slot 1).
+__device__ __forceinline__ void route_count(const Digest& dg, bool valid, bool active, bool use32, bool f32)
+{
+    if (!dg.counts) return;
+    const unsigned long long nv = __popcll(__ballot(valid));
+    const unsigned long long na = __popcll(__ballot(active));
+    if (threadIdx.x == 0) {
+        if (f32) {
+            if (use32 && na) atomicAdd(dg.counts + 1, na);
+        } else {
+            if (!use32 && na) atomicAdd(dg.counts, na);
+            if (nv > na) atomicAdd(dg.counts + 2, nv - na);
+        }
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double v)

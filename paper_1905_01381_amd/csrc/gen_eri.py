@@ -33,6 +33,33 @@ import sys
 
 DIRS = "xyz"
 
+# Arithmetic type of the code being emitted: "double" (FP64 path) or "float"
+# (the precision-routed FP32 path).  Set through set_prec().
+PREC = {"T": "double"}
+
+
+def set_prec(t: str) -> None:
+    PREC["T"] = t
+
+
+def T_() -> str:
+    return PREC["T"]
+
+
+def lit(x) -> str:
+    """A numeric literal of the current precision."""
+    v = repr(float(x))
+    return v + "f" if PREC["T"] == "float" else v
+
+
+def red(name: str) -> str:
+    return name + ("f" if PREC["T"] == "float" else "")
+
+
+def cvx(expr: str) -> str:
+    """A double-valued load converted to the current precision."""
+    return f"(float){expr}" if PREC["T"] == "float" else expr
+
 
 def comps(l):
     return [(i, j, l - i - j) for i in range(l, -1, -1) for j in range(l - i, -1, -1)]
@@ -107,10 +134,10 @@ class VRR:
                 f2 = sub(f1, i)
                 c = self.get(e, f2, m)
                 d = self.get(e, f2, m + 1)
-                terms.append(f"{float(f1[i])} * (oo2q * {c} - rq2 * {d})")
+                terms.append(f"{lit(f1[i])} * (oo2q * {c} - rq2 * {d})")
             if e[i] > 0:
                 g = self.get(sub(e, i), f1, m + 1)
-                terms.append(f"{float(e[i])} * oo2pq * {g}")
+                terms.append(f"{lit(e[i])} * oo2pq * {g}")
         else:
             i = next(k for k in range(3) if e[k] > 0)
             e1 = sub(e, i)
@@ -122,8 +149,8 @@ class VRR:
                 e2 = sub(e1, i)
                 c = self.get(e2, f, m)
                 d = self.get(e2, f, m + 1)
-                terms.append(f"{float(e1[i])} * (oo2p * {c} - rp2 * {d})")
-        self.out(f"const double {nm} = " + " + ".join(terms) + ";")
+                terms.append(f"{lit(e1[i])} * (oo2p * {c} - rp2 * {d})")
+        self.out(f"const {T_()} {nm} = " + " + ".join(terms) + ";")
         self.count += 1
         self.memo[key] = nm
         return nm
@@ -145,40 +172,41 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
     Gaussian-product data, the Boys function F_0..F_L and the VRR
     coefficients (the loops are closed by the caller)."""
     L = la + lb + lc + ld
+    T = T_()
     out("for (int kp = 0; kp < bra.nprim2; ++kp) {")
-    out("  const double p = bra.p[kp * bra.stride + ib];")
-    out("  const double Kab = bra.K[kp * bra.stride + ib];")
-    out("  if (Kab == 0.0) continue;")
-    out("  const double oo2p = bra.oo2p[kp * bra.stride + ib];")
-    out("  const double Px = bra.Px[kp * bra.stride + ib], Py = bra.Py[kp * bra.stride + ib], Pz = bra.Pz[kp * bra.stride + ib];")
+    out(f"  const {T} p = bra.p[kp * bra.stride + ib];")
+    out(f"  const {T} Kab = bra.K[kp * bra.stride + ib];")
+    out("  if (Kab == 0) continue;")
+    out(f"  const {T} oo2p = bra.oo2p[kp * bra.stride + ib];")
+    out(f"  const {T} Px = bra.Px[kp * bra.stride + ib], Py = bra.Py[kp * bra.stride + ib], Pz = bra.Pz[kp * bra.stride + ib];")
     if la + lb > 0:
-        out("  const double PAx = bra.PAx[kp * bra.stride + ib], PAy = bra.PAy[kp * bra.stride + ib], PAz = bra.PAz[kp * bra.stride + ib];")
+        out(f"  const {T} PAx = bra.PAx[kp * bra.stride + ib], PAy = bra.PAy[kp * bra.stride + ib], PAz = bra.PAz[kp * bra.stride + ib];")
     out("  for (int kq = 0; kq < ket.nprim2; ++kq) {")
-    out("    const double q = ket.p[kq * ket.stride + jk];")
-    out("    const double Kcd = ket.K[kq * ket.stride + jk];")
-    out("    const double oo2q = ket.oo2p[kq * ket.stride + jk];")
-    out("    const double Qx = ket.Px[kq * ket.stride + jk], Qy = ket.Py[kq * ket.stride + jk], Qz = ket.Pz[kq * ket.stride + jk];")
+    out(f"    const {T} q = ket.p[kq * ket.stride + jk];")
+    out(f"    const {T} Kcd = ket.K[kq * ket.stride + jk];")
+    out(f"    const {T} oo2q = ket.oo2p[kq * ket.stride + jk];")
+    out(f"    const {T} Qx = ket.Px[kq * ket.stride + jk], Qy = ket.Py[kq * ket.stride + jk], Qz = ket.Pz[kq * ket.stride + jk];")
     if lc + ld > 0:
-        out("    const double QCx = ket.PAx[kq * ket.stride + jk], QCy = ket.PAy[kq * ket.stride + jk], QCz = ket.PAz[kq * ket.stride + jk];")
-    out("    const double pq = p + q;")
-    out("    const double rs = rsqrt_f64(pq);")
-    out("    const double inv = rs * rs;")
-    out("    const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
-    out("    const double rho = p * q * inv;")
-    out("    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
-    out(f"    double F[{L + 1}];")
-    out(f"    boys_fp64<{L}>(T, boys_tab, F);")
-    out("    const double pref = Kab * Kcd * rs;")
+        out(f"    const {T} QCx = ket.PAx[kq * ket.stride + jk], QCy = ket.PAy[kq * ket.stride + jk], QCz = ket.PAz[kq * ket.stride + jk];")
+    out(f"    const {T} pq = p + q;")
+    out(f"    const {T} rs = {'rsqrt_f64' if T == 'double' else 'rsqrt_f32'}(pq);")
+    out(f"    const {T} inv = rs * rs;")
+    out(f"    const {T} PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
+    out(f"    const {T} rho = p * q * inv;")
+    out(f"    const {T} T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
+    out(f"    {T} F[{L + 1}];")
+    out(f"    {'boys_fp64' if T == 'double' else 'boys_fp32'}<{L}>(T, boys_tab, F);")
+    out(f"    const {T} pref = Kab * Kcd * rs;")
     for m in range(L + 1):
-        out(f"    const double ss{m} = pref * F[{m}];")
+        out(f"    const {T} ss{m} = pref * F[{m}];")
     if L > 0:
-        out("    const double oo2pq = 0.5 * inv;")
+        out(f"    const {T} oo2pq = {lit(0.5)} * inv;")
         if la + lb > 0:
-            out("    const double WPx = -q * inv * PQx, WPy = -q * inv * PQy, WPz = -q * inv * PQz;")
-            out("    const double rp2 = q * inv * oo2p;")
+            out(f"    const {T} WPx = -q * inv * PQx, WPy = -q * inv * PQy, WPz = -q * inv * PQz;")
+            out(f"    const {T} rp2 = q * inv * oo2p;")
         if lc + ld > 0:
-            out("    const double WQx = p * inv * PQx, WQy = p * inv * PQy, WQz = p * inv * PQz;")
-            out("    const double rq2 = p * inv * oo2q;")
+            out(f"    const {T} WQx = p * inv * PQx, WQy = p * inv * PQy, WQz = p * inv * PQz;")
+            out(f"    const {T} rq2 = p * inv * oo2q;")
 
 
 def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
@@ -189,9 +217,15 @@ def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
     eidx = {e: k for k, e in enumerate(es)}
     fidx = {f: k for k, f in enumerate(fs)}
     nE, nF = len(es), len(fs)
-    out(f"double acc[{nE * nF}];")
-    out(f"#pragma unroll")
-    out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = 0.0;")
+    T = T_()
+    if T == "float":
+        out(f"float acc32[{nE * nF}], cmp32[{nE * nF}];")
+        out(f"#pragma unroll")
+        out(f"for (int t = 0; t < {nE * nF}; ++t) acc32[t] = cmp32[t] = 0;")
+    else:
+        out(f"double acc[{nE * nF}];")
+        out(f"#pragma unroll")
+        out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = 0;")
     emit_prim_header(out, la, lb, lc, ld)
     inner = Emitter("    ")
     vrr = VRR(inner, L)
@@ -201,9 +235,21 @@ def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
     out.lines.extend(inner.lines)
     for e in es:
         for f in fs:
-            out(f"    acc[{eidx[e] * nF + fidx[f]}] += {vrr.memo[(e, f, 0)]};")
+            k = eidx[e] * nF + fidx[f]
+            if T == "float":
+                out(f"    kahan_add(acc32[{k}], cmp32[{k}], {vrr.memo[(e, f, 0)]});")
+            else:
+                out(f"    acc[{k}] += {vrr.memo[(e, f, 0)]};")
     out("  }")
     out("}")
+    if T == "float":
+        # fold the compensated FP32 sums into FP64; the horizontal transfer
+        # and the digestion run in FP64
+        out(f"double acc[{nE * nF}];")
+        out(f"#pragma unroll")
+        out(f"for (int t = 0; t < {nE * nF}; ++t) acc[t] = (double)acc32[t] - (double)cmp32[t];")
+        set_prec("double")
+        T = "double"
     # HRR bra: (a,b|f] for every ket target f
     A_, B_, C_, D_ = comps(la), comps(lb), comps(lc), comps(ld)
     hb: dict = {}
@@ -220,7 +266,7 @@ def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
         x = bra(add(a, i), sub(b, i), f)
         y = bra(a, sub(b, i), f)
         nm = f"hb{tag(a)}_{tag(b)}_{tag(f)}"
-        out(f"const double {nm} = {x} + AB{DIRS[i]} * {y};")
+        out(f"const {T} {nm} = {x} + AB{DIRS[i]} * {y};")
         hb[key] = nm
         return nm
 
@@ -238,12 +284,12 @@ def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
         x = ket(a, b, add(c, i), sub(d, i))
         y = ket(a, b, c, sub(d, i))
         nm = f"hk{tag(a)}_{tag(b)}_{tag(c)}_{tag(d)}"
-        out(f"const double {nm} = {x} + CD{DIRS[i]} * {y};")
+        out(f"const {T} {nm} = {x} + CD{DIRS[i]} * {y};")
         hk[key] = nm
         return nm
 
     nv = len(A_) * len(B_) * len(C_) * len(D_)
-    out(f"double v[{nv}];")
+    out(f"{T} v[{nv}];")
     n = 0
     for a in A_:
         for b in B_:
@@ -275,44 +321,44 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
     out("  if (js >= 0) {")
     for k in range(nc):
         for l in range(nd):
-            out(f"    const double xcd{k}{l} = ld_x(dg, fc + {k}, fd + {l}, m);")
+            out(f"    const {T_()} xcd{k}{l} = {cvx(f'ld_x(dg, fc + {k}, fd + {l}, m)')};")
     for i in range(na):
         for j in range(nb):
-            out(f"    const double xab{i}{j} = ld_x(dg, fa + {i}, fb + {j}, m);")
+            out(f"    const {T_()} xab{i}{j} = {cvx(f'ld_x(dg, fa + {i}, fb + {j}, m)')};")
     for i in range(na):
         for j in range(nb):
             s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
-            out(f"    {{ const double s = red_j(2.0 * ({s})); if (dj == 0 && rowv) atomic_add(dg.J + jidx(dg, fa + {i}, fb + {j}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s})); if (dj == 0 && rowv) atomic_add(dg.J + jidx(dg, fa + {i}, fb + {j}, js), s); }}")
     for k in range(nc):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xab{i}{j}" for i in range(na) for j in range(nb))
-            out(f"    {{ const double s = red_i(2.0 * ({s})); if (bi == 0 && colv) atomic_add(dg.J + jidx(dg, fc + {k}, fd + {l}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({lit(2)} * ({s})); if (bi == 0 && colv) atomic_add(dg.J + jidx(dg, fc + {k}, fd + {l}, js), s); }}")
     out("  }")
     out("  if (ks >= 0) {")
     for j in range(nb):
         for l in range(nd):
-            out(f"    const double xbd{j}{l} = ld_x(dg, fb + {j}, fd + {l}, m);")
+            out(f"    const {T_()} xbd{j}{l} = {cvx(f'ld_x(dg, fb + {j}, fd + {l}, m)')};")
     for j in range(nb):
         for k in range(nc):
-            out(f"    const double xbc{j}{k} = ld_x(dg, fb + {j}, fc + {k}, m);")
+            out(f"    const {T_()} xbc{j}{k} = {cvx(f'ld_x(dg, fb + {j}, fc + {k}, m)')};")
     for i in range(na):
         for l in range(nd):
-            out(f"    const double xad{i}{l} = ld_x(dg, fa + {i}, fd + {l}, m);")
+            out(f"    const {T_()} xad{i}{l} = {cvx(f'ld_x(dg, fa + {i}, fd + {l}, m)')};")
     for i in range(na):
         for k in range(nc):
-            out(f"    const double xac{i}{k} = ld_x(dg, fa + {i}, fc + {k}, m);")
+            out(f"    const {T_()} xac{i}{k} = {cvx(f'ld_x(dg, fa + {i}, fc + {k}, m)')};")
     for i in range(na):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xbd{j}{l}" for j in range(nb) for l in range(nd))
-            out(f"    {{ const double s = red_i(red_j({s})); if (lane == 0) atomic_add(dg.K + kidx(dg, fa + {i}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({red('red_j')}({s})); if (lane == 0) atomic_add(dg.K + kidx(dg, fa + {i}, fc + {k}, ks), s); }}")
     for i in range(na):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
-            out(f"    {{ const double s = red_i({s}); if (bi == 0 && colv) atomic_add(dg.K + kidx(dg, fa + {i}, fd + {l}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({s}); if (bi == 0 && colv) atomic_add(dg.K + kidx(dg, fa + {i}, fd + {l}, ks), s); }}")
     for j in range(nb):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
-            out(f"    {{ const double s = red_j({s}); if (dj == 0 && rowv) atomic_add(dg.K + kidx(dg, fb + {j}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(dg.K + kidx(dg, fb + {j}, fc + {k}, ks), s); }}")
     for j in range(nb):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
@@ -370,9 +416,16 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
     nodes = 0
     for sub_ in stage_subsets(la, lb, lc, ld):
         out("{")
-        out(f"  double acc[{len(sub_)}];")
+        out(f"  {T_()} acc[{len(sub_)}];")
         out(f"  #pragma unroll")
-        out(f"  for (int t = 0; t < {len(sub_)}; ++t) acc[t] = 0.0;")
+        out(f"  for (int t = 0; t < {len(sub_)}; ++t) acc[t] = 0;")
+        if T_() == "float":
+            out(f"  float cmp[{len(sub_)}];")
+            out(f"  #pragma unroll")
+            out(f"  for (int t = 0; t < {len(sub_)}; ++t) cmp[t] = 0;")
+            store = lambda k: f"(double)acc[{k}] - (double)cmp[{k}]"
+        else:
+            store = lambda k: f"acc[{k}]"
         hdr = Emitter(out.ind + "  ")
         emit_prim_header(hdr, la, lb, lc, ld)
         out.lines.extend(hdr.lines)
@@ -383,14 +436,18 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
         nodes += vrr.count
         out.lines.extend(inner.lines)
         for k, (e, f) in enumerate(sub_):
-            out(f"      acc[{k}] += {vrr.memo[(e, f, 0)]};")
+            if T_() == "float":
+                out(f"      kahan_add(acc[{k}], cmp[{k}], {vrr.memo[(e, f, 0)]});")
+            else:
+                out(f"      acc[{k}] += {vrr.memo[(e, f, 0)]};")
         out("    }")
         out("  }")
         for k, (e, f) in enumerate(sub_):
-            out(f"  STS({G0 + eidx[e] * nF + fidx[f]}, acc[{k}]);")
+            out(f"  STS({G0 + eidx[e] * nF + fidx[f]}, {store(k)});")
         out("}")
         out("stage_fence();")
     A_, B_, C_, D_ = comps(la), comps(lb), comps(lc), comps(ld)
+    set_prec("double")  # transfers and digestion in FP64 in both paths
     # bra transfer, one ket target f at a time
     for f in fs:
         out("{")
@@ -408,7 +465,7 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
             for b in B_:
                 collect(a, b)
         for e in sorted(needed, key=lambda x: eidx[x]):
-            out(f"  const double g{tag(e)} = STL({G0 + eidx[e] * nF + fidx[f]});")
+            out(f"  const {T_()} g{tag(e)} = STL({G0 + eidx[e] * nF + fidx[f]});")
         memo = {}
 
         def bra(a, b):
@@ -421,7 +478,7 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
             x = bra(add(a, i), sub(b, i))
             y = bra(a, sub(b, i))
             nm = f"h{tag(a)}_{tag(b)}"
-            out(f"  const double {nm} = {x} + AB{DIRS[i]} * {y};")
+            out(f"  const {T_()} {nm} = {x} + AB{DIRS[i]} * {y};")
             memo[(a, b)] = nm
             return nm
 
@@ -448,7 +505,7 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
             for d in D_:
                 collectk(c, d)
         for f in sorted(needed, key=lambda x: fidx[x]):
-            out(f"  const double q{tag(f)} = STL({HB0 + ab * nF + fidx[f]});")
+            out(f"  const {T_()} q{tag(f)} = STL({HB0 + ab * nF + fidx[f]});")
         memo = {}
 
         def ket(c, d):
@@ -461,7 +518,7 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
             x = ket(add(c, i), sub(d, i))
             y = ket(c, sub(d, i))
             nm = f"k{tag(c)}_{tag(d)}"
-            out(f"  const double {nm} = {x} + CD{DIRS[i]} * {y};")
+            out(f"  const {T_()} {nm} = {x} + CD{DIRS[i]} * {y};")
             memo[(c, d)] = nm
             return nm
 
@@ -498,23 +555,24 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
         ("K_bd", [(j, l) for j in range(nb) for l in range(nd)], [(i, k) for i in range(na) for k in range(nc)],
          lambda o, s: Vi(s[0], o[0], s[1], o[1]), ("fa", "fc"), ("K", "fb", "fd", "ks"), "none", "active", ""),
     ]
-    for (name, outs, sums, vfn, (xr, xc), (arr, dr, dc, slot), red, guard, scale) in specs:
+    for (name, outs, sums, vfn, (xr, xc), (arr, dr, dc, slot), rd, guard, scale) in specs:
         isJ = arr == "J"
         for o in outs:
             out("{")
             for t, sidx in enumerate(sums):
-                out(f"  const double w{t} = STL({vfn(o, sidx)});")
+                out(f"  const {T_()} w{t} = STL({vfn(o, sidx)});")
             out("  for (int m = 0; m < dg.nX; ++m) {")
             out(f"    const int {slot} = dg.{'jslot' if isJ else 'kslot'}[m];")
             out(f"    if ({slot} < 0) continue;")
-            terms = " + ".join(f"w{t} * ld_x(dg, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)" for t, sidx in enumerate(sums))
-            val = f"{scale}({terms})"
-            if red == "red_all":
-                val = f"red_i(red_j({val}))"
-            elif red != "none":
-                val = f"{red}({val})"
+            terms = " + ".join(f"w{t} * {cvx(f'ld_x(dg, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)')}" for t, sidx in enumerate(sums))
+            sc = f"{lit(2)} * " if scale else ""
+            val = f"{sc}({terms})"
+            if rd == "red_all":
+                val = f"{red('red_i')}({red('red_j')}({val}))"
+            elif rd != "none":
+                val = f"{red(rd)}({val})"
             idxf = "jidx" if isJ else "kidx"
-            out(f"    const double s = {val};")
+            out(f"    const {T_()} s = {val};")
             out(f"    if ({guard}) atomic_add(dg.{arr} + {idxf}(dg, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s);")
             out("  }")
             out("}")
@@ -534,95 +592,124 @@ HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 // shell quartet) with Coulomb/exchange digestion."""
 
 
+def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
+    """One J/K kernel of a class in one precision.  Both kernels of a class
+    walk the same tasks and take the same per-step routing decision; each
+    evaluates only the steps of its own precision."""
+    cn = class_name(la, lb, lc, ld)
+    L = la + lb + lc + ld
+    staged = is_staged(la, lb, lc, ld)
+    nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+    set_prec(prec)
+    body = Emitter("    ")
+    dig = Emitter("    ")
+    if staged:
+        nvrr = emit_staged_eri(body, la, lb, lc, ld)
+    else:
+        _, nvrr = emit_eri_body(body, la, lb, lc, ld)
+    set_prec("double")
+    if staged:
+        emit_staged_digest(dig, la, lb, lc, ld)
+    else:
+        emit_digest(dig, la, lb, lc, ld)
+    stage_n = stage_layout(la, lb, lc, ld)[3] if staged else 0
+    f32 = prec == "float"
+    kname = f"eri_jk{'32' if f32 else ''}_{cn}"
+    o = Emitter("")
+    o(f"// ({cn}) L={L}: {nv} integrals, {nvrr} VRR nodes per primitive quartet, {prec}")
+    same_ab = int(la == lb)
+    same_cd = int(lc == ld)
+    same_cls = int((la, lb) == (lc, ld))
+    o(f"__global__ __launch_bounds__(64) void {kname}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab)")
+    o("{")
+    if f32:
+        o("  if (dg.mode != 1) return;")
+    o("  const int lane = threadIdx.x;")
+    o("  const int bi = lane >> 3, dj = lane & 7;")
+    if staged:
+        o(f"  const stage_rsrc srs = stage_make(dg.stage + (size_t)blockIdx.x * ({stage_n} * 64), {stage_n} * 512);")
+        o("  const int svo = lane * 8;")
+        o("#define STL(i) stage_load(srs, svo, (i))")
+        o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
+    o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
+    o("    const int4 tk = tm.tasks[task];")
+    o("    const int a_idx = tk.x, b_idx = tk.y * 8 + bi, d_idx = tk.z * 8 + dj;")
+    o(f"    const bool rowv = b_idx < ({'a_idx + 1' if same_ab else 'tm.nsl_b'});")
+    o("    const bool dval = d_idx < tm.nsl_d;")
+    o("    const int a = tm.shl_a[a_idx];")
+    o("    const int b = tm.shl_b[rowv ? b_idx : tk.y * 8];")
+    o("    const int d = tm.shl_d[dval ? d_idx : tk.z * 8];")
+    o("    const int ib = tm.ppos[a * tm.nshell + b];")
+    o("    const int fa = bra.fa[ib], fb = bra.fb[ib];")
+    t = "double"
+    if lb > 0:
+        o(f"    const {t} ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
+    o(f"    const int c_lo = tk.w & 0xffff;")
+    o(f"    const int c_hi = tk.w >> 16;")
+    o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
+    o("      const int c = tm.shl_c[c_idx];")
+    o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
+    o("      bool active = rowv && colv;")
+    if same_cls:
+        o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
+    o(f"      const int jk = tm.ppos[c * tm.nshell + (colv ? d : {'c' if same_cd else 'd'})];")
+    o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
+    o("      const bool valid = active;")
+    o("      double bnd = 0.0;")
+    o("      if (dg.mode != 0 || dg.skip > 0.0) bnd = quartet_bound(dg, bra.Q[ib], ket.Q[jk], a, b, c, d);")
+    o("      if (dg.skip > 0.0 && active) active = bnd >= dg.skip;")
+    o("      const bool use32 = dg.mode == 1 && wave_max(active ? bnd : 0.0) < dg.fp32_below;")
+    if f32:
+        o("      route_count(dg, valid, active, use32, true);")
+        o("      if (!use32) continue;")
+    else:
+        o("      route_count(dg, valid, active, use32, false);")
+        o("      if (use32) continue;")
+    o("      if (!__any(active)) continue;")
+    if ld > 0:
+        o(f"      const {t} CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
+    o("      double deg = active ? 1.0 : 0.0;")
+    if same_ab:
+        o("      if (a == b) deg *= 0.5;")
+    if same_cd:
+        o("      if (c == d) deg *= 0.5;")
+    if same_cls:
+        o("      if (a == c && b == d) deg *= 0.5;")
+    body.lines = ["  " + x if x else x for x in body.lines]
+    o(body.text())
+    if not staged:
+        o(f"      #pragma unroll")
+        o(f"      for (int t = 0; t < {nv}; ++t) v[t] *= deg;")
+    dig.lines = ["  " + x if x else x for x in dig.lines]
+    o(dig.text())
+    o("    }")
+    o("  }")
+    if staged:
+        o("#undef STL")
+        o("#undef STS")
+    o("}")
+    o("")
+    return o.text(), nvrr, stage_n
+
+
 def gen(lmax: int) -> dict:
     pcls, classes = all_classes(lmax)
     files = {}
     stats = []
     stage_sizes = {}
     for (la, lb, lc, ld) in classes:
+        cn = class_name(la, lb, lc, ld)
+        nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+        k64, nvrr, stage_n = emit_jk_kernel(la, lb, lc, ld, "double")
+        k32, _, _ = emit_jk_kernel(la, lb, lc, ld, "float")
+        stage_sizes[(la, lb, lc, ld)] = stage_n
+        stats.append((cn, nv, nvrr))
         o = Emitter("")
         o(HEADER)
         o('#include "eri_common.hpp"')
         o("")
-        cn = class_name(la, lb, lc, ld)
-        L = la + lb + lc + ld
-        # J/K kernel
-        staged = is_staged(la, lb, lc, ld)
-        body = Emitter("    ")
-        dig = Emitter("    ")
-        nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        if staged:
-            nvrr = emit_staged_eri(body, la, lb, lc, ld)
-            emit_staged_digest(dig, la, lb, lc, ld)
-            stage_n = stage_layout(la, lb, lc, ld)[3]
-        else:
-            nv, nvrr = emit_eri_body(body, la, lb, lc, ld)
-            emit_digest(dig, la, lb, lc, ld)
-            stage_n = 0
-        stage_sizes[(la, lb, lc, ld)] = stage_n
-        stats.append((cn, nv, nvrr))
-        o(f"// ({cn}) L={L}: {nv} integrals, {nvrr} VRR nodes per primitive quartet")
-        same_ab = int(la == lb)
-        same_cd = int(lc == ld)
-        same_cls = int((la, lb) == (lc, ld))
-        o(f"__global__ __launch_bounds__(64) void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab)")
-        o("{")
-        o("  const int lane = threadIdx.x;")
-        o("  const int bi = lane >> 3, dj = lane & 7;")
-        if staged:
-            o(f"  const stage_rsrc srs = stage_make(dg.stage + (size_t)blockIdx.x * ({stage_n} * 64), {stage_n} * 512);")
-            o("  const int svo = lane * 8;")
-            o("#define STL(i) stage_load(srs, svo, (i))")
-            o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
-        o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
-        o("    const int4 tk = tm.tasks[task];")
-        o("    const int a_idx = tk.x, b_idx = tk.y * 8 + bi, d_idx = tk.z * 8 + dj;")
-        o(f"    const bool rowv = b_idx < ({'a_idx + 1' if same_ab else 'tm.nsl_b'});")
-        o("    const bool dval = d_idx < tm.nsl_d;")
-        o("    const int a = tm.shl_a[a_idx];")
-        o("    const int b = tm.shl_b[rowv ? b_idx : tk.y * 8];")
-        o("    const int d = tm.shl_d[dval ? d_idx : tk.z * 8];")
-        o("    const int ib = tm.ppos[a * tm.nshell + b];")
-        o("    const int fa = bra.fa[ib], fb = bra.fb[ib];")
-        if lb > 0:
-            o("    const double ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
-        o(f"    const int c_lo = tk.w & 0xffff;")
-        o(f"    const int c_hi = tk.w >> 16;")
-        o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
-        o("      const int c = tm.shl_c[c_idx];")
-        o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
-        o("      bool active = rowv && colv;")
-        if same_cls:
-            o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
-        o(f"      const int jk = tm.ppos[c * tm.nshell + (colv ? d : {'c' if same_cd else 'd'})];")
-        o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
-        o("      if (dg.skip > 0.0 && active) active = quartet_bound(dg, bra.Q[ib], ket.Q[jk], a, b, c, d) >= dg.skip;")
-        o("      if (!__any(active)) continue;")
-        if ld > 0:
-            o("      const double CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
-        body.ind = "      "
-        body.lines = ["  " + x if x else x for x in body.lines]
-        o("      double deg = active ? 1.0 : 0.0;")
-        if same_ab:
-            o("      if (a == b) deg *= 0.5;")
-        if same_cd:
-            o("      if (c == d) deg *= 0.5;")
-        if same_cls:
-            o("      if (a == c && b == d) deg *= 0.5;")
-        o(body.text())
-        if not staged:
-            o(f"      #pragma unroll")
-            o(f"      for (int t = 0; t < {nv}; ++t) v[t] *= deg;")
-        dig.lines = ["  " + x if x else x for x in dig.lines]
-        o(dig.text())
-        o("    }")
-        o("  }")
-        if staged:
-            o("#undef STL")
-            o("#undef STS")
-        o("}")
-        o("")
-        # block kernel (tests and Schwarz): quartet list -> raw blocks
+        o.lines.append(k64)
+        # block kernel (tests and Schwarz): quartet list -> raw blocks, FP64
         body2 = Emitter("  ")
         emit_eri_body(body2, la, lb, lc, ld)
         o(f"__global__ __launch_bounds__(64) void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab)")
@@ -639,6 +726,12 @@ def gen(lmax: int) -> dict:
         o(f"  for (int u = 0; u < {nv}; ++u) out[(long long)t * {nv} + u] = v[u];")
         o("}")
         files[f"eri_{cn}.hip"] = o.text() + "\n"
+        o = Emitter("")
+        o(HEADER)
+        o('#include "eri_common.hpp"')
+        o("")
+        o.lines.append(k32)
+        files[f"eri_{cn}_f32.hip"] = o.text() + "\n"
     o = Emitter("")
     o(HEADER)
     o("#pragma once")
@@ -646,15 +739,17 @@ def gen(lmax: int) -> dict:
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         o(f"__global__ void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
+        o(f"__global__ void eri_jk32_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
         o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
     # dispatch tables
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; void (*jk)(PairSet, PairSet, TaskMap, Digest, const double*); void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, eri_jk_{cn}, eri_block_{cn}}},")
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)

@@ -234,3 +234,62 @@ def test_one_electron_against_oracle(spd_case, torch_cuda):
     got = gb.one_electron("nuclear", charges=mol.charges, centers=mol.atoms).cpu().numpy()
     ref = ob.one_electron("nuclear", charges=mol.charges, centers=mol.atoms)
     assert rel_err(got, ref) < 1e-12
+
+
+def _energy(P, J, K):
+    return 2.0 * float(np.sum(P * J)) - float(np.sum(P * K))
+
+
+def test_routed_all_fp32(spd_case, torch_cuda):
+    """Every batch forced to FP32: errors at FP32 level, counters say so."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, gb, P = spd_case
+    J, K = _jk_gpu(torch, gb, [P], [1], th=cq.thresholds(mode=1, fp32_below=1e300))
+    st = gb.build_stats()
+    assert st["fp64"] == 0 and st["fp32"] > 0 and st["skipped"] == 0
+    Jr, Kr = ob.jk(P)
+    scale = np.abs(Jr).max()
+    ej = np.abs(J[0] - Jr).max() / scale
+    ek = np.abs(K[0] - Kr).max() / scale
+    E = _energy(P, Jr, Kr)
+    dE = abs(_energy(P, J[0], K[0]) - E)
+    print(f"all-FP32 max|dJ|/max|J| {ej:.2e} max|dK|/max|J| {ek:.2e} dE {dE:.2e} (E {E:.3f})", flush=True)
+    # Forcing every batch to FP32 is a stress case: the FP32 Obara-Saika terms
+    # PA [..] + WP [..]^(m+1) cancel for distant pairs (large |P-A|), so
+    # exchange elements lose ~2 digits beyond FP32 rounding.  Such pairs have
+    # small Schwarz factors, which is why routing sends only small-bound
+    # batches to FP32 (checked to 1e-6 Eh in the mixed test below).
+    assert 1e-12 < ej < 5e-6 and 1e-12 < ek < 5e-5
+    assert dE < 1e-5 * abs(E), dE
+
+
+def test_routed_mixed_threshold(torch_cuda):
+    """12 atoms of 2s1p (exponents 0.3..30, localized): the smallest bound
+    threshold that sends some batches to FP32 and keeps others in FP64; the
+    energy stays within 1e-6 Eh of the oracle there and at 1e-5."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, P = case_real(12, inputs.SHELLS_2S1P, seed=21, lo=0.3, hi=30.0)
+    gb = cq.Basis.from_molecule(w.mol)
+    J64, K64 = _jk_gpu(torch, gb, [P], [1])
+    st64 = gb.build_stats()
+    Jr, Kr = ob.jk(P)
+    assert rel_err(J64[0], Jr) < TOL_JK and rel_err(K64[0], Kr) < TOL_JK
+    E = _energy(P, Jr, Kr)
+    split = None
+    for thr in (1e-5, 1e-4, 1e-3, 1e-2, 3e-2, 1e-1):
+        J, K = _jk_gpu(torch, gb, [P], [1], th=cq.thresholds(mode=1, fp32_below=thr))
+        st = gb.build_stats()
+        assert st["fp32"] + st["fp64"] == st64["fp64"]
+        dE = abs(_energy(P, J[0], K[0]) - E)
+        frac = st["fp32"] / (st["fp32"] + st["fp64"])
+        print(f"fp32_below {thr:.0e}: fp32 fraction {frac:.3f} dE {dE:.2e} "
+              f"max|dJ| {np.abs(J[0] - Jr).max():.2e} max|dK| {np.abs(K[0] - Kr).max():.2e}", flush=True)
+        if thr == 1e-5:
+            assert dE < 1e-6
+        if st["fp32"] > 0 and st["fp64"] > 0:
+            split = thr
+            assert dE < 1e-6
+            break
+    assert split is not None
