@@ -170,6 +170,68 @@ cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t strea
 cq_status cq_profile(cq_basis b, int enable);
 cq_status cq_profile_read(cq_basis b, int maxn, int* cls, double* ms, long long* count, int* n);
 
+/* ---- real-time propagation (paper: "Real-Time Electronic Dynamics") ---- */
+
+typedef struct cq_rt_s* cq_rt;
+
+#define CQ_RT_EM2 0       /* explicit 2nd-order Magnus (the paper's EM2), 2 builds/step */
+#define CQ_RT_MIDPOINT 1  /* self-consistent midpoint Magnus-2 corrector */
+#define CQ_RT_LEARNED 2   /* MLP midpoint proposal, corrector as fallback */
+
+/* Propagator for a closed-shell density (P per spin, total 2P) in the
+ * Loewdin orthonormal basis.  All matrix arguments are DEVICE buffers,
+ * row-major [nbf][nbf], copied at creation:
+ *   h   real core Hamiltonian (AO)        X   real S^{-1/2} (AO)
+ *   Dz  real dipole-length operator <m|z - origin|n> (AO)
+ *   P0  complex orthonormal-basis density P'(t0) = S^{1/2} P S^{1/2},
+ *       interleaved (re, im)
+ * F(P) = h + 2 J[Re P] - K[Re P] - i K[Im P] (Eq. 2c_fock, scalar part,
+ * reading A1); the field-free propagation uses U = exp(-i dt F') with
+ * F' = X F X (Taylor degree 16 with scaling and squaring).  The first three
+ * steps of the midpoint and learned modes use EM2 (the paper's seed step).
+ * Work runs on `stream` (kept by the handle). */
+cq_status cq_rt_create(cq_basis b, const double* h, const double* X, const double* Dz, const double* P0,
+                       double dt, int mode, hipStream_t stream, cq_rt* out);
+cq_status cq_rt_destroy(cq_rt rt);
+cq_status cq_rt_set_mode(cq_rt rt, int mode);
+/* Midpoint convergence: max |P_mid^(i+1) - P_mid^(i)| < sc_tol within
+ * max_iter builds (else CQ_ENOTCONV); learned proposals are accepted when
+ * max |(P_k + P_{k+1})/2 - P_mid^pred| < accept_tol. */
+cq_status cq_rt_set_params(cq_rt rt, double sc_tol, int max_iter, double accept_tol);
+/* Advance nsteps steps; per step (HOST arrays, each may be NULL): the
+ * electronic energy Re Tr[P(h + F)] (costs one extra, uncounted build),
+ * the electronic dipole -2 Re Tr[D_z P] (Eq. td_expectation), and the
+ * number of Fock builds the step used.  Synchronizes the stream. */
+cq_status cq_rt_step(cq_rt rt, int nsteps, double* energy, double* dipole, int* builds);
+/* Current orthonormal density (DEVICE complex [nbf][nbf]). */
+cq_status cq_rt_density(cq_rt rt, double* P, hipStream_t stream);
+/* out4 (HOST): steps, builds, accepted learned proposals, fallbacks. */
+cq_status cq_rt_stats(cq_rt rt, long long* out4);
+/* Learned proposal: record (features, converged midpoint) samples at
+ * samples_per_step fixed random elements of every midpoint step while
+ * enabled.  Proposal baseline B = (P_k + U_prev P_k U_prev^dagger)/2 with
+ * the previous step's propagator; features per element: B - P_k,
+ * P_k - P_{k-1}, P_{k-1} - P_{k-2}, B - P_k - (P_k - P_{k-1})/2 (re, im);
+ * target: converged midpoint - B; all scaled by their RMS over the samples;
+ * train the pointwise MLP (8 -> 32 tanh -> 2, FP32) with Adam on
+ * the GPU for `epochs` passes (one mini-batch per recorded step, learning
+ * rate lr; feature / target scales from the recorded samples); set / get
+ * the 354 FP32 weights [W1 32x8, b1 32, W2 2x32, b2 2] (HOST). */
+cq_status cq_rt_record(cq_rt rt, int enable, int samples_per_step, unsigned seed);
+cq_status cq_rt_recorded(cq_rt rt, int* nsteps);
+cq_status cq_rt_train(cq_rt rt, int epochs, float lr, float* loss);
+cq_status cq_rt_mlp_weights(cq_rt rt, const float* set354, float* get354);
+cq_status cq_rt_mlp_scales(cq_rt rt, float* feature_scale8, double* out_scale);
+
+/* Test exports: U = exp(-i dt H) for a Hermitian DEVICE complex H [n][n];
+ * MLP loss 1/(2N) sum |y - t|^2 and its gradient for DEVICE weights w354,
+ * samples X [ns][8], targets Y [ns][2]; one Adam step (beta 0.9/0.999,
+ * eps 1e-8) on DEVICE w, g, m, v (354 each). */
+cq_status cq_expm(int n, const double* H, double dt, double* U, hipStream_t stream);
+cq_status cq_mlp_eval(const float* w354, const float* X, const float* Y, int ns, float* grad, float* loss,
+                      hipStream_t stream);
+cq_status cq_mlp_adam(float* w, const float* g, float* m, float* v, float lr, int step, hipStream_t stream);
+
 /* ---- test-only exports ------------------------------------------------ */
 
 /* Boys function F_m(T) for m = 0..mmax (mmax <= 16) at n points, FP64.

@@ -70,7 +70,8 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     t0 = time.time()
     extra = extra or []
     os.makedirs(OBJ, exist_ok=True)
-    srcs = generate(verbose) + [os.path.join(CSRC, "cq_api.hip"), os.path.join(CSRC, "one_electron.hip")]
+    srcs = generate(verbose) + [os.path.join(CSRC, "cq_api.hip"), os.path.join(CSRC, "one_electron.hip"),
+                                 os.path.join(CSRC, "rt.hip")]
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     objs, logs = [], []
     with cf.ThreadPoolExecutor(jobs) as ex:
@@ -78,7 +79,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
             objs.append(obj)
             logs.append(log)
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocblas"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     if verbose:

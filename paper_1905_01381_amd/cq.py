@@ -61,10 +61,29 @@ def lib():
         L.cq_quartet_counts.argtypes = [vp, i, ip, llp, ip]
         L.cq_profile.argtypes = [vp, i]
         L.cq_build_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong), vp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.cq_rt_create.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, i, vp, ctypes.POINTER(vp)]
+        L.cq_rt_destroy.argtypes = [vp]
+        L.cq_rt_set_mode.argtypes = [vp, i]
+        L.cq_rt_set_params.argtypes = [vp, ctypes.c_double, i, ctypes.c_double]
+        L.cq_rt_step.argtypes = [vp, i, dp, dp, ip]
+        L.cq_rt_density.argtypes = [vp, vp, vp]
+        L.cq_rt_stats.argtypes = [vp, llp]
+        L.cq_rt_record.argtypes = [vp, i, i, ctypes.c_uint]
+        L.cq_rt_recorded.argtypes = [vp, ip]
+        L.cq_rt_train.argtypes = [vp, i, ctypes.c_float, fp]
+        L.cq_rt_mlp_weights.argtypes = [vp, fp, fp]
+        L.cq_rt_mlp_scales.argtypes = [vp, fp, dp]
+        L.cq_expm.argtypes = [i, vp, ctypes.c_double, vp, vp]
+        L.cq_mlp_eval.argtypes = [vp, vp, vp, i, vp, vp, vp]
+        L.cq_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, i, vp]
         L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
         for name in ("cq_basis_create", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
                      "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile",
-                     "cq_profile_read", "cq_build_stats"):
+                     "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
+                     "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
+                     "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
+                     "cq_mlp_eval", "cq_mlp_adam"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -241,3 +260,113 @@ def boys(mmax: int, T, stream=None):
     F = torch.empty((T.numel(), mmax + 1), dtype=torch.float64, device=T.device)
     _check(lib().cq_boys(int(mmax), int(T.numel()), _ptr(T), _ptr(F), _stream(stream)))
     return F
+
+
+RT_EM2, RT_MIDPOINT, RT_LEARNED = 0, 1, 2
+MLP_PARAMS = 354
+
+
+class RT:
+    """Real-time propagator handle (cq_rt_*)."""
+
+    def __init__(self, basis: "Basis", h, X, Dz, P0, dt: float, mode: int = RT_EM2, stream=None):
+        import torch
+        n = basis.nbf
+        for m in (h, X, Dz):
+            _req_dev(m, torch.float64, (n, n))
+        _req_dev(P0, torch.complex128, (n, n))
+        self.basis = basis
+        self.n = n
+        self._keep = (h, X, Dz, P0)
+        hdl = ctypes.c_void_p()
+        _check(lib().cq_rt_create(basis.h, _ptr(h), _ptr(X), _ptr(Dz), _ptr(P0), float(dt), int(mode),
+                                  _stream(stream), ctypes.byref(hdl)))
+        self.h = hdl
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().cq_rt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mode(self, mode: int):
+        _check(lib().cq_rt_set_mode(self.h, int(mode)))
+
+    def set_params(self, sc_tol=1e-10, max_iter=30, accept_tol=1e-8):
+        _check(lib().cq_rt_set_params(self.h, float(sc_tol), int(max_iter), float(accept_tol)))
+
+    def step(self, nsteps: int, energy: bool = False, dipole: bool = True):
+        E = np.zeros(nsteps)
+        mu = np.zeros(nsteps)
+        nb = np.zeros(nsteps, dtype=np.int32)
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        _check(lib().cq_rt_step(self.h, int(nsteps), E.ctypes.data_as(dp) if energy else None,
+                                mu.ctypes.data_as(dp) if dipole else None, nb.ctypes.data_as(ip)))
+        return E, mu, nb
+
+    def density(self, stream=None):
+        import torch
+        P = torch.empty((self.n, self.n), dtype=torch.complex128, device="cuda")
+        _check(lib().cq_rt_density(self.h, _ptr(P), _stream(stream)))
+        return P
+
+    def stats(self) -> dict:
+        out = (ctypes.c_longlong * 4)()
+        _check(lib().cq_rt_stats(self.h, out))
+        return {"steps": out[0], "builds": out[1], "accepted": out[2], "fallbacks": out[3]}
+
+    def record(self, enable=True, samples_per_step=4096, seed=1):
+        _check(lib().cq_rt_record(self.h, int(enable), int(samples_per_step), int(seed)))
+
+    def train(self, epochs: int, lr: float = 1e-3) -> float:
+        loss = ctypes.c_float()
+        _check(lib().cq_rt_train(self.h, int(epochs), float(lr), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def weights(self, set_=None):
+        fp = ctypes.POINTER(ctypes.c_float)
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        if set_ is not None:
+            w = np.ascontiguousarray(set_, dtype=np.float32)
+            _check(lib().cq_rt_mlp_weights(self.h, w.ctypes.data_as(fp), out.ctypes.data_as(fp)))
+        else:
+            _check(lib().cq_rt_mlp_weights(self.h, None, out.ctypes.data_as(fp)))
+        return out
+
+
+def _rt_scales(self):
+    fp = ctypes.POINTER(ctypes.c_float)
+    xs = np.zeros(8, dtype=np.float32)
+    ys = ctypes.c_double()
+    _check(lib().cq_rt_mlp_scales(self.h, xs.ctypes.data_as(fp), ctypes.byref(ys)))
+    return xs, float(ys.value)
+
+
+RT.scales = _rt_scales
+
+
+def expm(H, dt: float, stream=None):
+    """exp(-i dt H) for a device complex128 Hermitian H."""
+    import torch
+    _req_dev(H, torch.complex128)
+    U = torch.empty_like(H)
+    _check(lib().cq_expm(int(H.shape[0]), _ptr(H), float(dt), _ptr(U), _stream(stream)))
+    return U
+
+
+def mlp_eval(w, X, Y, stream=None):
+    """Loss and gradient of the midpoint MLP on device FP32 samples."""
+    import torch
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().cq_mlp_eval(_ptr(w), _ptr(X), _ptr(Y), int(X.shape[0]), _ptr(g), _ptr(loss), _stream(stream)))
+    return loss, g
+
+
+def mlp_adam(w, g, m, v, lr: float, step: int, stream=None):
+    _check(lib().cq_mlp_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), float(lr), int(step), _stream(stream)))
