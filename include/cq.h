@@ -93,6 +93,30 @@ cq_status cq_basis_create(int nshell, const double* xyz, const int* l, const int
                           const double* alpha, const double* coef, hipStream_t stream,
                           cq_basis* out);
 
+/* A batch of independent molecules in one handle (the batched uneven
+ * launch: one integral pass serves every molecule, each class in a single
+ * launch whose tasks span all molecules; quartets never mix molecules).
+ *   nmol             number of molecules, >= 1
+ *   nshell_mol[nmol] host, shells of each molecule (>= 1 each); the shell
+ *                    arrays (xyz, l, nprim, alpha, coef: as in
+ *                    cq_basis_create) list molecule 0's shells, then
+ *                    molecule 1's, ...
+ * Matrices of a batch handle (densities, J, K, cq_schwarz output) are the
+ * concatenation of the molecules' row-major [nbf_m][nbf_m] blocks, molecule
+ * m starting at element sum_{k<m} nbf_k^2.  Shell-pair quantities
+ * (cq_schwarz) are concatenated [ns_m][ns_m] blocks likewise.  The
+ * two-component, one-electron and real-time entry points take
+ * single-molecule handles only (CQ_EUNSUPPORTED otherwise).  Allocates and
+ * synchronizes like cq_basis_create. */
+cq_status cq_basis_create_batch(int nmol, const int* nshell_mol, const double* xyz, const int* l,
+                                const int* nprim, const double* alpha, const double* coef,
+                                hipStream_t stream, cq_basis* out);
+
+/* Molecules in a handle (1 for cq_basis_create; -1 on NULL) and the basis
+ * functions of each, written to HOST nbf_mol[nmol]. */
+int cq_basis_nmol(cq_basis b);
+cq_status cq_basis_mol_nbf(cq_basis b, int* nbf_mol);
+
 /* Release a basis and all of its device memory (synchronizes the device). */
 cq_status cq_basis_destroy(cq_basis b);
 
@@ -102,13 +126,16 @@ int cq_basis_nshell(cq_basis b);
 
 /* Schwarz factors Q_ab = sqrt(max_{m in a, n in b} (mn|mn)) (paper:
  * "Reference Wave Functions", integral screening).  Computed once at basis
- * creation and cached.  If Q is not NULL, the [nshell][nshell] matrix is
- * copied to the DEVICE buffer Q (stream-ordered). */
+ * creation and cached.  If Q is not NULL, the [nshell][nshell] matrix (for
+ * a batch: the per-molecule [ns_m][ns_m] blocks, concatenated) is copied to
+ * the DEVICE buffer Q (stream-ordered). */
 cq_status cq_schwarz(cq_basis b, double* Q, hipStream_t stream);
 
 /* Coulomb and exchange matrices of nmat densities in one integral pass.
  *   nmat        1..CQ_MAX_DENSITIES
  *   P[nmat]     host array of device pointers to the densities X_m
+ *               (nbf x nbf row-major; for a batch handle, the concatenated
+ *               per-molecule blocks described at cq_basis_create_batch)
  *   sym[nmat]   +1 if X_m is symmetric, -1 if antisymmetric (only that part
  *               of X_m is used; e.g. the imaginary part of a Hermitian
  *               density is antisymmetric, paper: the remark on the
@@ -161,6 +188,22 @@ cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, in
  * basis, written to HOST out3: [0] evaluated in FP64, [1] evaluated in FP32
  * (precision-routed mode), [2] removed by screening.  Synchronizes `stream`. */
 cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t stream);
+
+/* Autotuner for the electron-repulsion launches of this handle: for every
+ * class it times candidate task shapes (length of the c range one wave
+ * walks: the default, half, twice and four times it) and grid caps (one wave
+ * per task, or 2048 waves looping over tasks) with HIP events, each `reps`
+ * times (1..100), on a synthetic density of nmat slots, and keeps the
+ * fastest for every later build on the handle.  Results do not depend on the
+ * choice beyond the order of floating-point atomic additions.  Synchronizes
+ * `stream`; overwrites the handle's work buffers only. */
+cq_status cq_autotune(cq_basis b, int nmat, int reps, hipStream_t stream);
+
+/* The launch plan per class (tuned or default): for k < cap,
+ * rec[7k..7k+6] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks) and
+ * ms[k] = best time measured by cq_autotune (0 if not tuned); *n = classes
+ * with work.  Host arrays. */
+cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
 
 /* Per-class launch timing with HIP events recorded on the launch stream
  * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.

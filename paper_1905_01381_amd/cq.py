@@ -45,6 +45,12 @@ def lib():
         vp, dp, ip, i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int
         L.cq_last_error.restype = ctypes.c_char_p
         L.cq_basis_create.argtypes = [i, dp, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
+        L.cq_basis_create_batch.argtypes = [i, ip, dp, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
+        L.cq_basis_nmol.argtypes = [vp]
+        L.cq_basis_nmol.restype = i
+        L.cq_basis_mol_nbf.argtypes = [vp, ip]
+        L.cq_autotune.argtypes = [vp, i, i, vp]
+        L.cq_autotune_read.argtypes = [vp, i, ip, ctypes.POINTER(ctypes.c_float), ip]
         L.cq_basis_destroy.argtypes = [vp]
         L.cq_basis_nbf.argtypes = [vp]
         L.cq_basis_nbf.restype = i
@@ -78,7 +84,8 @@ def lib():
         L.cq_mlp_eval.argtypes = [vp, vp, vp, i, vp, vp, vp]
         L.cq_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, i, vp]
         L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
-        for name in ("cq_basis_create", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
+        for name in ("cq_basis_create", "cq_basis_create_batch", "cq_basis_mol_nbf", "cq_autotune",
+                     "cq_autotune_read", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
                      "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile",
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
@@ -127,9 +134,12 @@ def thresholds(skip: float = 0.0, fp32_below: float = 0.0, mode: int = 0, accumu
 
 
 class Basis:
-    """A libcq basis handle (device resident)."""
+    """A libcq basis handle (device resident).  With ``nshell_mol`` the shell
+    arrays hold several molecules one after another and the handle is a
+    batch: its matrices are flat tensors of the concatenated per-molecule
+    [nbf_m, nbf_m] blocks (see ``pack`` / ``unpack``)."""
 
-    def __init__(self, shell_xyz, shell_l, nprim, alpha, coef, stream=None):
+    def __init__(self, shell_xyz, shell_l, nprim, alpha, coef, stream=None, nshell_mol=None):
         xyz = np.ascontiguousarray(shell_xyz, dtype=np.float64).reshape(-1)
         l = np.ascontiguousarray(shell_l, dtype=np.int32)
         npr = np.ascontiguousarray(nprim, dtype=np.int32)
@@ -137,17 +147,71 @@ class Basis:
         c = np.ascontiguousarray(coef, dtype=np.float64)
         h = ctypes.c_void_p()
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
-        _check(lib().cq_basis_create(int(l.size), xyz.ctypes.data_as(dp), l.ctypes.data_as(ip),
-                                     npr.ctypes.data_as(ip), a.ctypes.data_as(dp), c.ctypes.data_as(dp),
-                                     _stream(stream), ctypes.byref(h)))
+        if nshell_mol is None:
+            _check(lib().cq_basis_create(int(l.size), xyz.ctypes.data_as(dp), l.ctypes.data_as(ip),
+                                         npr.ctypes.data_as(ip), a.ctypes.data_as(dp), c.ctypes.data_as(dp),
+                                         _stream(stream), ctypes.byref(h)))
+        else:
+            nsm = np.ascontiguousarray(nshell_mol, dtype=np.int32)
+            if int(nsm.sum()) != l.size:
+                raise ValueError("nshell_mol does not add up to the number of shells")
+            _check(lib().cq_basis_create_batch(int(nsm.size), nsm.ctypes.data_as(ip), xyz.ctypes.data_as(dp),
+                                               l.ctypes.data_as(ip), npr.ctypes.data_as(ip),
+                                               a.ctypes.data_as(dp), c.ctypes.data_as(dp), _stream(stream),
+                                               ctypes.byref(h)))
         self.h = h
         self.nbf = lib().cq_basis_nbf(h)
         self.nshell = lib().cq_basis_nshell(h)
         self.shell_l = l.copy()
+        self.nmol = lib().cq_basis_nmol(h)
+        nb = np.zeros(self.nmol, np.int32)
+        _check(lib().cq_basis_mol_nbf(h, nb.ctypes.data_as(ip)))
+        self.mol_nbf = [int(x) for x in nb]
+        self.mol_off = [0]
+        for n in self.mol_nbf:
+            self.mol_off.append(self.mol_off[-1] + n * n)
+        self.nel = self.mol_off[-1]
+        self.batch = nshell_mol is not None
 
     @classmethod
     def from_molecule(cls, mol, stream=None) -> "Basis":
         return cls(mol.shell_xyz, mol.shell_l, mol.nprim, mol.alpha, mol.coef, stream)
+
+    @classmethod
+    def from_molecules(cls, mols, stream=None) -> "Basis":
+        """A batch handle over a list of molecules."""
+        return cls(np.concatenate([np.asarray(m.shell_xyz).reshape(-1, 3) for m in mols]),
+                   np.concatenate([m.shell_l for m in mols]), np.concatenate([m.nprim for m in mols]),
+                   np.concatenate([m.alpha for m in mols]), np.concatenate([m.coef for m in mols]), stream,
+                   nshell_mol=[len(m.shell_l) for m in mols])
+
+    def pack(self, mats):
+        """Concatenate per-molecule [nbf_m, nbf_m] device matrices into one flat batch tensor."""
+        import torch
+        return torch.cat([m.reshape(-1) for m in mats]).contiguous()
+
+    def unpack(self, flat):
+        """Views of a flat batch tensor as the per-molecule [nbf_m, nbf_m] blocks."""
+        return [flat[self.mol_off[i]:self.mol_off[i + 1]].view(n, n) for i, n in enumerate(self.mol_nbf)]
+
+    def autotune(self, nmat: int = 1, reps: int = 1, stream=None) -> list:
+        """Time candidate task shapes and grid caps per class and keep the fastest."""
+        _check(lib().cq_autotune(self.h, int(nmat), int(reps), _stream(stream)))
+        return self.plan()
+
+    def plan(self) -> list:
+        """The launch plan per class: (la, lb, lc, ld), c-range length, grid cap, tasks, tuned ms."""
+        n = ctypes.c_int()
+        rec = np.zeros(7 * 32, np.int32)
+        ms = np.zeros(32, np.float32)
+        _check(lib().cq_autotune_read(self.h, 32, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                      ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
+        out = []
+        for k in range(min(n.value, 32)):
+            r = rec[7 * k:7 * k + 7]
+            out.append({"cls": tuple(int(x) for x in r[:4]), "cl": int(r[4]), "grid": int(r[5]),
+                        "tasks": int(r[6]), "ms": float(ms[k])})
+        return out
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -162,6 +226,8 @@ class Basis:
 
     def schwarz(self, stream=None):
         import torch
+        if self.batch:
+            raise ValueError("schwarz() returns the single-molecule [nshell, nshell] matrix")
         Q = torch.empty((self.nshell, self.nshell), dtype=torch.float64, device="cuda")
         _check(lib().cq_schwarz(self.h, _ptr(Q), _stream(stream)))
         return Q
@@ -176,7 +242,7 @@ class Basis:
         wj = [want_j] * n if isinstance(want_j, bool) else list(want_j)
         wk = [want_k] * n if isinstance(want_k, bool) else list(want_k)
         for p in Ps:
-            _req_dev(p, torch.float64, (self.nbf, self.nbf))
+            _req_dev(p, torch.float64, (self.nel,) if self.batch else (self.nbf, self.nbf))
         if out is None:
             J = [torch.empty_like(Ps[m]) if wj[m] else None for m in range(n)]
             K = [torch.empty_like(Ps[m]) if wk[m] else None for m in range(n)]

@@ -112,7 +112,7 @@ struct PairSet {
     int npair, nprim2, stride, pad_;
     const int* sa;   // first shell (angular momentum la)
     const int* sb;   // second shell
-    const int* fa;   // first function of sa
+    const int* fa;   // first function of sa, counted from its molecule's first
     const int* fb;
     const double* ABx;  // A - B
     const double* ABy;
@@ -129,20 +129,32 @@ struct PairSet {
     const double* K;    // c_a c_b exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p
 };
 
-// Work of one class (la lb|lc ld): one task per (a, 8 consecutive b, 8
-// consecutive d, a range of c); the wave loops over c.  Lane 8 i + j holds the quartet
-// (a b_i | c d_j).  Shells of each angular momentum are listed in index order
-// (shl_*), and ppos maps an oriented shell pair (higher l first; a >= b for
-// equal l) to its position in its pair class.
+// One molecule of a basis (a batch holds many): its shells and functions are
+// contiguous; shell-pair tables (ppos, block maxima) and the packed densities
+// and partial sums are block-diagonal, one block per molecule.
+struct MolInfo {
+    long long xoff;   // first element of the molecule's [nbf][nbf] block
+    long long soff;   // first element of its [ns][ns] shell-pair block
+    int f0, nbf;      // first function, functions
+    int s0, ns;       // first shell, shells
+};
+
+// Work of one class (la lb|lc ld): one task per (molecule, a, 8 consecutive
+// b, 8 consecutive d, a range of c); the wave loops over c.  Lane 8 i + j
+// holds the quartet (a b_i | c d_j).  Shells of each angular momentum are
+// listed molecule by molecule in index order (shl_*); ppos maps an oriented
+// shell pair (higher l first; a >= b for equal l) of one molecule to its
+// position in its pair class.
 struct TaskMap {
-    const int4* tasks;  // (a index, b chunk, d chunk, c_lo | c_hi << 16)
-    const int* ppos;    // [nshell * nshell]
+    const int4* tasks;  // (a index, first b index, first d index, first c index)
+    const int4* tasks2; // (end of b range, end of d range, molecule, last c index)
+    const int* ppos;    // block-diagonal [ns][ns] per molecule
     const int* shl_a;
     const int* shl_b;
     const int* shl_c;
     const int* shl_d;
-    int ntask, nshell;
-    int nsl_a, nsl_b, nsl_c, nsl_d;
+    const MolInfo* mols;
+    int ntask, pad_;
 };
 
 // Sums over the 8 lanes sharing i (lanes 8i..8i+7) / sharing j.
@@ -161,16 +173,17 @@ __device__ __forceinline__ double red_i(double v)
     return v;
 }
 
-// Densities and outputs of one build, interleaved [mu][nu][slot].
+// Densities and outputs of one build, interleaved [mu][nu][slot] within each
+// molecule's block.
 struct Digest {
-    const double* X;  // [nbf][nbf][nX], scaled by component factors
-    double* J;        // [nbf][nbf][nJ] partial sums J'
-    double* K;        // [nbf][nbf][nK] partial sums K'
+    const double* X;  // per molecule [nbf][nbf][nX], scaled by component factors
+    double* J;        // per molecule [nbf][nbf][nJ] partial sums J'
+    double* K;        // per molecule [nbf][nbf][nK] partial sums K'
     int nbf, nX, nJ, nK;
     int jslot[CQ_MAX_MAT];
     int kslot[CQ_MAX_MAT];
     double skip;          // density-weighted Schwarz threshold (0: none)
-    const double* pmax;   // [nshell][nshell] max |X| per shell block
+    const double* pmax;   // block-diagonal [ns][ns] per molecule: max |X| per shell block
     int nshell;
     int stage_blocks;     // waves that own a stage region (grid limit of staged classes)
     double* stage;        // per-wave private stage, [stage_blocks][class stage size][64]
@@ -180,18 +193,47 @@ struct Digest {
     unsigned long long* counts;  // [3]: quartets evaluated in FP64, in FP32, skipped by screening
 };
 
-__device__ __forceinline__ double ld_x(const Digest& dg, int mu, int nu, int m)
+// One molecule's blocks as seen by a task: uniform base pointers plus
+// 32-bit offsets (function indices are local to the molecule; a molecule
+// holds at most 16383 functions, so [nbf][nbf][8] offsets fit in 32 bits).
+struct MolView {
+    const double* X;
+    double* J;
+    double* K;
+    const int* ppos;
+    const double* pmax;
+    int nbf, s0, ns;
+};
+
+__device__ __forceinline__ MolView mol_view(const Digest& dg, const TaskMap& tm, int m)
 {
-    return dg.X[((long long)mu * dg.nbf + nu) * dg.nX + m];
+    const MolInfo mi = tm.mols[m];
+    MolView v;
+    v.X = dg.X + mi.xoff * dg.nX;
+    v.J = dg.J + mi.xoff * dg.nJ;
+    v.K = dg.K + mi.xoff * dg.nK;
+    v.ppos = tm.ppos + mi.soff;
+    v.pmax = dg.pmax + mi.soff;
+    v.nbf = mi.nbf;
+    v.s0 = mi.s0;
+    v.ns = mi.ns;
+    return v;
 }
-__device__ __forceinline__ long long jidx(const Digest& dg, int mu, int nu, int s)
+__device__ __forceinline__ double ld_x(const Digest& dg, const MolView& mc, int mu, int nu, int m)
 {
-    return ((long long)mu * dg.nbf + nu) * dg.nJ + s;
+    return mc.X[(mu * mc.nbf + nu) * dg.nX + m];
 }
-__device__ __forceinline__ long long kidx(const Digest& dg, int mu, int nu, int s)
+__device__ __forceinline__ int jidx(const Digest& dg, const MolView& mc, int mu, int nu, int s)
 {
-    return ((long long)mu * dg.nbf + nu) * dg.nK + s;
+    return (mu * mc.nbf + nu) * dg.nJ + s;
 }
+__device__ __forceinline__ int kidx(const Digest& dg, const MolView& mc, int mu, int nu, int s)
+{
+    return (mu * mc.nbf + nu) * dg.nK + s;
+}
+// offset of the oriented shell pair (a, b) (global shell indices) in the
+// molecule's [ns][ns] tables
+__device__ __forceinline__ int spair(const MolView& mc, int a, int b) { return (a - mc.s0) * mc.ns + (b - mc.s0); }
 
 __device__ __forceinline__ void atomic_add(double* p, double v)
 {
@@ -270,11 +312,10 @@ __device__ __forceinline__ void stage_store(stage_rsrc r, int voff, int i, doubl
 // forwarded in registers (which would defeat the staging).
 __device__ __forceinline__ void stage_fence() { __asm__ volatile("" ::: "memory"); }
 
-__device__ __forceinline__ double quartet_bound(const Digest& dg, double qab, double qcd, int a, int b, int c, int d)
+__device__ __forceinline__ double quartet_bound(const MolView& mc, double qab, double qcd, int a, int b, int c, int d)
 {
-    const double* pm = dg.pmax;
-    const int n = dg.nshell;
-    double m = fmax(fmax(pm[a * n + b], pm[c * n + d]), fmax(pm[a * n + c], pm[a * n + d]));
-    m = fmax(m, fmax(pm[b * n + c], pm[b * n + d]));
+    const double* pm = mc.pmax;
+    double m = fmax(fmax(pm[spair(mc, a, b)], pm[spair(mc, c, d)]), fmax(pm[spair(mc, a, c)], pm[spair(mc, a, d)]));
+    m = fmax(m, fmax(pm[spair(mc, b, c)], pm[spair(mc, b, d)]));
     return qab * qcd * m;
 }

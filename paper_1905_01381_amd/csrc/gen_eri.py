@@ -321,48 +321,48 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
     out("  if (js >= 0) {")
     for k in range(nc):
         for l in range(nd):
-            out(f"    const {T_()} xcd{k}{l} = {cvx(f'ld_x(dg, fc + {k}, fd + {l}, m)')};")
+            out(f"    const {T_()} xcd{k}{l} = {cvx(f'ld_x(dg, mc, fc + {k}, fd + {l}, m)')};")
     for i in range(na):
         for j in range(nb):
-            out(f"    const {T_()} xab{i}{j} = {cvx(f'ld_x(dg, fa + {i}, fb + {j}, m)')};")
+            out(f"    const {T_()} xab{i}{j} = {cvx(f'ld_x(dg, mc, fa + {i}, fb + {j}, m)')};")
     for i in range(na):
         for j in range(nb):
             s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s})); if (dj == 0 && rowv) atomic_add(dg.J + jidx(dg, fa + {i}, fb + {j}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s})); if (dj == 0 && rowv) atomic_add(mc.J + jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     for k in range(nc):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xab{i}{j}" for i in range(na) for j in range(nb))
-            out(f"    {{ const {T_()} s = {red('red_i')}({lit(2)} * ({s})); if (bi == 0 && colv) atomic_add(dg.J + jidx(dg, fc + {k}, fd + {l}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({lit(2)} * ({s})); if (bi == 0 && colv) atomic_add(mc.J + jidx(dg, mc, fc + {k}, fd + {l}, js), s); }}")
     out("  }")
     out("  if (ks >= 0) {")
     for j in range(nb):
         for l in range(nd):
-            out(f"    const {T_()} xbd{j}{l} = {cvx(f'ld_x(dg, fb + {j}, fd + {l}, m)')};")
+            out(f"    const {T_()} xbd{j}{l} = {cvx(f'ld_x(dg, mc, fb + {j}, fd + {l}, m)')};")
     for j in range(nb):
         for k in range(nc):
-            out(f"    const {T_()} xbc{j}{k} = {cvx(f'ld_x(dg, fb + {j}, fc + {k}, m)')};")
+            out(f"    const {T_()} xbc{j}{k} = {cvx(f'ld_x(dg, mc, fb + {j}, fc + {k}, m)')};")
     for i in range(na):
         for l in range(nd):
-            out(f"    const {T_()} xad{i}{l} = {cvx(f'ld_x(dg, fa + {i}, fd + {l}, m)')};")
+            out(f"    const {T_()} xad{i}{l} = {cvx(f'ld_x(dg, mc, fa + {i}, fd + {l}, m)')};")
     for i in range(na):
         for k in range(nc):
-            out(f"    const {T_()} xac{i}{k} = {cvx(f'ld_x(dg, fa + {i}, fc + {k}, m)')};")
+            out(f"    const {T_()} xac{i}{k} = {cvx(f'ld_x(dg, mc, fa + {i}, fc + {k}, m)')};")
     for i in range(na):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xbd{j}{l}" for j in range(nb) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_i')}({red('red_j')}({s})); if (lane == 0) atomic_add(dg.K + kidx(dg, fa + {i}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({red('red_j')}({s})); if (lane == 0) atomic_add(mc.K + kidx(dg, mc, fa + {i}, fc + {k}, ks), s); }}")
     for i in range(na):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
-            out(f"    {{ const {T_()} s = {red('red_i')}({s}); if (bi == 0 && colv) atomic_add(dg.K + kidx(dg, fa + {i}, fd + {l}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({s}); if (bi == 0 && colv) atomic_add(mc.K + kidx(dg, mc, fa + {i}, fd + {l}, ks), s); }}")
     for j in range(nb):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(dg.K + kidx(dg, fb + {j}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fc + {k}, ks), s); }}")
     for j in range(nb):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
-            out(f"    if (active) atomic_add(dg.K + kidx(dg, fb + {j}, fd + {l}, ks), {s});")
+            out(f"    if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), {s});")
     out("  }")
     out("}")
 
@@ -564,7 +564,7 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
             out("  for (int m = 0; m < dg.nX; ++m) {")
             out(f"    const int {slot} = dg.{'jslot' if isJ else 'kslot'}[m];")
             out(f"    if ({slot} < 0) continue;")
-            terms = " + ".join(f"w{t} * {cvx(f'ld_x(dg, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)')}" for t, sidx in enumerate(sums))
+            terms = " + ".join(f"w{t} * {cvx(f'ld_x(dg, mc, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)')}" for t, sidx in enumerate(sums))
             sc = f"{lit(2)} * " if scale else ""
             val = f"{sc}({terms})"
             if rd == "red_all":
@@ -573,7 +573,7 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
                 val = f"{red(rd)}({val})"
             idxf = "jidx" if isJ else "kidx"
             out(f"    const {T_()} s = {val};")
-            out(f"    if ({guard}) atomic_add(dg.{arr} + {idxf}(dg, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s);")
+            out(f"    if ({guard}) atomic_add(mc.{arr} + {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s);")
             out("  }")
             out("}")
 
@@ -633,30 +633,31 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
     o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
     o("    const int4 tk = tm.tasks[task];")
-    o("    const int a_idx = tk.x, b_idx = tk.y * 8 + bi, d_idx = tk.z * 8 + dj;")
-    o(f"    const bool rowv = b_idx < ({'a_idx + 1' if same_ab else 'tm.nsl_b'});")
-    o("    const bool dval = d_idx < tm.nsl_d;")
+    o("    const int4 tk2 = tm.tasks2[task];")
+    o("    const MolView mc = mol_view(dg, tm, tk2.z);")
+    o("    const int a_idx = tk.x, b_idx = tk.y + bi, d_idx = tk.z + dj;")
+    o("    const bool rowv = b_idx < tk2.x;")
+    o("    const bool dval = d_idx < tk2.y;")
     o("    const int a = tm.shl_a[a_idx];")
-    o("    const int b = tm.shl_b[rowv ? b_idx : tk.y * 8];")
-    o("    const int d = tm.shl_d[dval ? d_idx : tk.z * 8];")
-    o("    const int ib = tm.ppos[a * tm.nshell + b];")
+    o("    const int b = tm.shl_b[rowv ? b_idx : tk.y];")
+    o("    const int d = tm.shl_d[dval ? d_idx : tk.z];")
+    o("    const int ib = mc.ppos[spair(mc, a, b)];")
     o("    const int fa = bra.fa[ib], fb = bra.fb[ib];")
     t = "double"
     if lb > 0:
         o(f"    const {t} ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
-    o(f"    const int c_lo = tk.w & 0xffff;")
-    o(f"    const int c_hi = tk.w >> 16;")
+    o("    const int c_lo = tk.w, c_hi = tk2.w;")
     o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
     o("      const int c = tm.shl_c[c_idx];")
     o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
     o("      bool active = rowv && colv;")
     if same_cls:
         o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
-    o(f"      const int jk = tm.ppos[c * tm.nshell + (colv ? d : {'c' if same_cd else 'd'})];")
+    o(f"      const int jk = mc.ppos[spair(mc, c, colv ? d : {'c' if same_cd else 'd'})];")
     o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
     o("      const bool valid = active;")
     o("      double bnd = 0.0;")
-    o("      if (dg.mode != 0 || dg.skip > 0.0) bnd = quartet_bound(dg, bra.Q[ib], ket.Q[jk], a, b, c, d);")
+    o("      if (dg.mode != 0 || dg.skip > 0.0) bnd = quartet_bound(mc, bra.Q[ib], ket.Q[jk], a, b, c, d);")
     o("      if (dg.skip > 0.0 && active) active = bnd >= dg.skip;")
     o("      const bool use32 = dg.mode == 1 && wave_max(active ? bnd : 0.0) < dg.fp32_below;")
     if f32:

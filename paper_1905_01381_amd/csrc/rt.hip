@@ -639,6 +639,7 @@ extern "C" cq_status cq_rt_create(cq_basis b, const double* h, const double* X, 
     if (!b || !h || !X || !Dz || !P0) return cq_internal_fail(CQ_EINVAL, "NULL argument");
     if (!(dt > 0) || !std::isfinite(dt)) return cq_internal_fail(CQ_EINVAL, "dt must be positive");
     if (mode < 0 || mode > 2) return cq_internal_fail(CQ_EINVAL, "mode must be 0 (EM2), 1 (midpoint) or 2 (learned)");
+    if (cq_basis_nmol(b) != 1) return cq_internal_fail(CQ_EUNSUPPORTED, "real-time propagation takes a single-molecule basis");
     cq_rt_s* r = new cq_rt_s();
     r->b = b;
     r->n = cq_basis_nbf(b);

@@ -162,16 +162,19 @@ def c4_sizes(seed: int = 0, nmol: int = 64) -> np.ndarray:
     return np.random.default_rng(seed).integers(10, 121, size=nmol)
 
 
-def c4(seed: int = 0, nmol: int = 64) -> list[Workload]:
-    """64 molecules of U{10..120} atoms; molecule i draws from
+def c4_molecule(i: int, seed: int = 0, nmol: int = 64) -> Workload:
+    """Molecule i of the batch: c4_sizes()[i] atoms drawn from
     default_rng([seed, i]); nocc_i = 2 N_i."""
-    out = []
-    for i, n in enumerate(c4_sizes(seed, nmol)):
-        rng = np.random.default_rng([seed, i])
-        mol = make_molecule(int(n), SHELLS_3S2P1D, 0.1, 1.0e3, rng)
-        q = random_orbitals(mol.nbf, 2 * int(n), rng)
-        out.append(Workload(f"C4[{i}]", mol, q, False, 2 * int(n)))
-    return out
+    n = int(c4_sizes(seed, nmol)[i])
+    rng = np.random.default_rng([seed, i])
+    mol = make_molecule(n, SHELLS_3S2P1D, 0.1, 1.0e3, rng)
+    q = random_orbitals(mol.nbf, 2 * n, rng)
+    return Workload(f"C4[{i}]", mol, q, False, 2 * n)
+
+
+def c4(seed: int = 0, nmol: int = 64) -> list[Workload]:
+    """64 molecules of U{10..120} atoms (see c4_molecule)."""
+    return [c4_molecule(i, seed, nmol) for i in range(nmol)]
 
 
 def c5(seed: int = 0, natom: int = 60) -> Workload:

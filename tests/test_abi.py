@@ -42,3 +42,9 @@ def test_argument_errors_without_gpu_work():
     assert L.cq_jk_build(None, 1, None, None, None, None, None, None) == cq.CQ_EINVAL
     assert L.cq_boys(99, 1, None, None, None) == cq.CQ_EINVAL
     assert L.cq_basis_nbf(None) == -1
+    assert L.cq_basis_nmol(None) == -1
+    assert L.cq_basis_create_batch(0, None, None, None, None, None, None, None, ctypes.byref(h)) == cq.CQ_EINVAL
+    ns = (ctypes.c_int * 2)(3, 0)
+    assert L.cq_basis_create_batch(2, ns, None, None, None, None, None, None, ctypes.byref(h)) == cq.CQ_EINVAL
+    assert b"molecule 1" in L.cq_last_error()
+    assert L.cq_autotune(None, 1, 1, None) == cq.CQ_EINVAL
