@@ -12,6 +12,19 @@ timed region.
 Output: one JSON line (metric, value = builds/s, quartets/s, roofline of the
 dominant electron-repulsion kernel measured with HIP events inside the timed
 region, and the CPU oracle timed on a bounded sample).
+
+Other workloads (one JSON line each, same top-level keys; not the headline):
+  --workload c3   mixed-precision routed build vs FP64 on the 3s2p1d lattice
+                  recipe (skip 1e-11, FP32 below 1e-5): builds/s of both
+                  modes, |dE|, max|dJ|, max|dK|, FP64/FP32/skip counts;
+                  --atoms scales the molecule (200 = the full workload)
+  --workload c4   batched uneven build: one handle over the --nmol smallest
+                  molecules of the 64-molecule set, one launch per class
+                  spanning all of them, default vs autotuned plan, against one
+                  handle per molecule built in turn
+  --workload c5   real-time Magnus-2 steps (EM2) on the 60-atom Z=1 workload:
+                  time per step and per Fock build after an RHF ground state
+                  and a delta kick; --atoms scales the molecule
 """
 from __future__ import annotations
 
@@ -41,7 +54,169 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--atoms", type=int, default=0, help="c3/c5: atoms (0 = the full workload)")
+    ap.add_argument("--nmol", type=int, default=16, help="c4: number of molecules (smallest first)")
     return ap.parse_args()
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _ortho_density(S, Q):
+    lam, U = np.linalg.eigh(S)
+    X = (U / np.sqrt(lam)) @ U.T
+    C = X @ Q
+    return C @ C.T
+
+
+def bench_c3(a, torch, cq, inputs):
+    """Routed vs FP64 build on the 3s2p1d lattice recipe (full size: 200
+    atoms, 400 occupied orbitals)."""
+    natom = a.atoms or 200
+    w = inputs.c3(natom=natom, nocc=2 * natom)
+    gb = cq.Basis.from_molecule(w.mol)
+    S = gb.one_electron("overlap").cpu().numpy()
+    P = torch.from_numpy(np.ascontiguousarray(_ortho_density(S, w.orbitals))).cuda()
+    counts = sum(gb.quartet_counts().values())
+    _log(f"c3: {natom} atoms, nbf {gb.nbf}, {counts:.3e} unique quartets unscreened")
+    th64 = cq.thresholds(skip=1e-11)
+    thr = cq.thresholds(skip=1e-11, mode=1, fp32_below=1e-5)
+    out = {}
+    for name, th in (("fp64", th64), ("routed", thr)):
+        res = {}
+
+        def run():
+            res["r"] = gb.jk([P], th=th)
+        dt = _timed(torch, run, a.steps, a.warmup)
+        st = gb.build_stats()
+        J, K = res["r"].J[0], res["r"].K[0]
+        E = 2.0 * float((P * J).sum()) - float((P * K).sum())
+        out[name] = {"s_per_build": dt, "stats": st, "E2": E, "J": J, "K": K}
+        _log(f"c3 {name}: {dt:.3f} s/build, {st}")
+    dJ = float((out["routed"]["J"] - out["fp64"]["J"]).abs().max())
+    dK = float((out["routed"]["K"] - out["fp64"]["K"]).abs().max())
+    st = out["routed"]["stats"]
+    ev = st["fp64"] + st["fp32"]
+    return {
+        "metric": "J+K builds/sec at |dE|<=1e-6 Eh: precision-routed vs FP64 (skip 1e-11, FP32 below 1e-5)",
+        "value": 1.0 / out["routed"]["s_per_build"], "unit": "builds/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": out["routed"]["s_per_build"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"mixed-precision routed J/K: {natom} atoms 3s2p1d (3 primitives), nbf {gb.nbf}, "
+                               f"{2 * natom} occupied orbitals; skip 1e-11, FP32 below 1e-5", "nbf": gb.nbf,
+                   "quartets_unscreened": counts},
+        "fp64_builds_per_s": 1.0 / out["fp64"]["s_per_build"],
+        "speedup_routed_vs_fp64": out["fp64"]["s_per_build"] / out["routed"]["s_per_build"],
+        "dE_Eh": abs(out["routed"]["E2"] - out["fp64"]["E2"]), "E2_fp64": out["fp64"]["E2"],
+        "max_abs_dJ": dJ, "max_abs_dK": dK,
+        "fp32_fraction": st["fp32"] / ev if ev else 0.0,
+        "counts_routed": st, "counts_fp64": out["fp64"]["stats"],
+        "quartets_per_s_routed": ev / out["routed"]["s_per_build"],
+    }
+
+
+def bench_c4(a, torch, cq, inputs):
+    """Batched uneven build over the smallest molecules of the 64-molecule set."""
+    sizes = inputs.c4_sizes()
+    pick = [int(i) for i in np.argsort(sizes, kind="stable")[:a.nmol]]
+    ws = [inputs.c4_molecule(i) for i in pick]
+    gb = cq.Basis.from_molecules([w.mol for w in ws])
+    Ps = []
+    for w in ws:
+        g1 = cq.Basis.from_molecule(w.mol)
+        S = g1.one_electron("overlap").cpu().numpy()
+        Ps.append(torch.from_numpy(np.ascontiguousarray(_ortho_density(S, w.orbitals))).cuda())
+        g1.close()
+    P = gb.pack(Ps)
+    counts = sum(gb.quartet_counts().values())
+    _log(f"c4: {len(ws)} molecules ({min(sizes[pick])}..{max(sizes[pick])} atoms), nbf {gb.mol_nbf[0]}.."
+         f"{gb.mol_nbf[-1]}, {counts:.3e} quartets")
+    t_default = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
+    _log(f"c4 batched default plan: {t_default:.3f} s/build")
+    t0 = time.perf_counter()
+    plan = gb.autotune(nmat=1, reps=1)
+    t_tune = time.perf_counter() - t0
+    t_tuned = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
+    _log(f"c4 batched tuned plan: {t_tuned:.3f} s/build (autotune {t_tune:.1f} s)")
+    singles = [cq.Basis.from_molecule(w.mol) for w in ws]
+
+    def per_mol():
+        for g1, p in zip(singles, Ps):
+            g1.jk([p])
+    t_single = _timed(torch, per_mol, a.steps, a.warmup)
+    _log(f"c4 one handle per molecule: {t_single:.3f} s/build")
+    return {
+        "metric": "J+K builds/sec, batched uneven launch (all molecules per class launch, autotuned)",
+        "value": 1.0 / t_tuned, "unit": "builds/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": t_tuned * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched uneven J/K: the {len(ws)} smallest of 64 molecules of U{{10..120}} atoms, "
+                               f"3s2p1d; one J and one K each; FP64, no screening", "nmol": len(ws),
+                   "atoms": [int(sizes[i]) for i in pick], "quartets_per_build": counts},
+        "quartets_per_s": counts / t_tuned,
+        "batched_default_builds_per_s": 1.0 / t_default,
+        "per_molecule_builds_per_s": 1.0 / t_single,
+        "speedup_batched_tuned_vs_per_molecule": t_single / t_tuned,
+        "speedup_tuned_vs_default": t_default / t_tuned,
+        "autotune_s": t_tune,
+        "plan": [{"cls": "".join("spd"[x] for x in p["cls"]), "cl": p["cl"], "grid": p["grid"],
+                  "ms": round(p["ms"], 3)} for p in plan],
+    }
+
+
+def bench_c5(a, torch, cq, inputs):
+    """EM2 real-time steps on the Z=1 lattice workload after an RHF ground
+    state and a delta kick along z."""
+    from paper_1905_01381_amd import scf
+    natom = a.atoms or 60
+    w = inputs.c5(natom=natom)
+    gb = cq.Basis.from_molecule(w.mol)
+    t0 = time.perf_counter()
+    res = scf.rhf(gb, w.mol, natom // 2)
+    t_scf = time.perf_counter() - t0
+    _log(f"c5: {natom} atoms, nbf {gb.nbf}; RHF E = {res.energy:.8f} in {res.iterations} iterations ({t_scf:.1f} s)")
+    Dz = gb.one_electron("dipole", direction=2).cpu().numpy()
+    X = res.X
+    Sh = res.S @ X
+    Po = Sh @ res.P @ Sh
+    lam, U = np.linalg.eigh(X @ Dz @ X)
+    Uk = (U * np.exp(-1j * 1e-4 * lam)) @ U.T
+    P0 = Uk @ Po @ Uk.conj().T
+    d = lambda m: torch.from_numpy(np.ascontiguousarray(m)).cuda()
+    rt = cq.RT(gb, d(res.h), d(X), d(Dz), d(P0), 0.05, cq.RT_EM2)
+    if a.warmup > 0:
+        rt.step(a.warmup, dipole=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, mu, nb = rt.step(a.steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    counts = sum(gb.quartet_counts().values())
+    builds = float(np.mean(nb))
+    return {
+        "metric": "RT-TDSCF Magnus-2 steps/sec (EM2: two J/K builds per step)",
+        "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"RT-TDSCF: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, {natom // 2} doubly occupied; "
+                               f"kick 1e-4 a.u. along z, dt 0.05 a.u.; EM2", "nbf": gb.nbf,
+                   "quartets_per_build": counts},
+        "builds_per_step": builds, "s_per_build": dt / builds,
+        "quartets_per_s": counts * builds / dt, "scf_energy": res.energy, "dipole_last": float(mu[-1]),
+    }
 
 
 def build_inputs(torch, cq, inputs):
@@ -107,6 +282,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.workload != "c2":
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[a.workload]
+        print(json.dumps(fn(a, torch, cq, inputs)), flush=True)
+        return
     w, gb, P2 = build_inputs(torch, cq, inputs)
     G = torch.empty_like(P2)
     counts = gb.quartet_counts()

@@ -23,14 +23,17 @@
 __device__ __forceinline__ double rsqrt_f64(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsqrt_f32(float x) { return rsqrtf(x); }
 
+#define BOYS_TAB_L (BOYS_NINT * BOYS_NC)  // coefficients of one order F_L
+
+// tabL: the BOYS_NINT x BOYS_NC coefficients of order L (device or LDS).
 template <int L>
-__device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ tab, double* F)
+__device__ __forceinline__ void boys_fp64_tab(double T, const double* __restrict__ tabL, double* F)
 {
     if (T < BOYS_TC) {
         int k = (int)(T * (1.0 / BOYS_H));
         k = k < 0 ? 0 : (k > BOYS_NINT - 1 ? BOYS_NINT - 1 : k);
         const double x = (T - k * BOYS_H) * (2.0 / BOYS_H) - 1.0;
-        const double* c = tab + ((size_t)L * BOYS_NINT + k) * BOYS_NC;
+        const double* c = tabL + k * BOYS_NC;
         double b1 = 0.0, b2 = 0.0;
 #pragma unroll
         for (int j = BOYS_NC - 1; j >= 1; --j) {
@@ -56,27 +59,36 @@ __device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ t
     }
 }
 
+// tab: the whole table, orders 0..BOYS_LMAX.
+template <int L>
+__device__ __forceinline__ void boys_fp64(double T, const double* __restrict__ tab, double* F)
+{
+    boys_fp64_tab<L>(T, tab + (size_t)L * BOYS_TAB_L, F);
+}
+
 // FP32 Boys function for the precision-routed path.  The table of FP32
 // Chebyshev coefficients follows the FP64 table in the same allocation.
 // Large arguments (T >= BOYS_TC) and high orders (L >= 6) are evaluated in
 // FP64 and rounded, so only the low-order, small-argument part runs in FP32.
 #define BOYS_TAB_DOUBLES ((BOYS_LMAX + 1) * BOYS_NINT * BOYS_NC)
 
+// tabL: for L < 6 the FP32 coefficients of order L; for L >= 6 the FP64
+// coefficients of order L (only the FP64 evaluation uses a table then; the
+// large-argument branch uses none).
 template <int L>
-__device__ __forceinline__ void boys_fp32(float T, const double* __restrict__ tab, float* F)
+__device__ __forceinline__ void boys_fp32_tab(float T, const void* __restrict__ tabL, float* F)
 {
     if (L >= 6 || !(T < (float)BOYS_TC)) {
         double Fd[L + 1];
-        boys_fp64<L>((double)T, tab, Fd);
+        boys_fp64_tab<L>((double)T, (const double*)tabL, Fd);
 #pragma unroll
         for (int m = 0; m <= L; ++m) F[m] = (float)Fd[m];
         return;
     }
-    const float* tf = (const float*)(tab + BOYS_TAB_DOUBLES);
     int k = (int)(T * (1.0f / (float)BOYS_H));
     k = k < 0 ? 0 : (k > BOYS_NINT - 1 ? BOYS_NINT - 1 : k);
     const float x = (T - k * (float)BOYS_H) * (2.0f / (float)BOYS_H) - 1.0f;
-    const float* c = tf + ((size_t)L * BOYS_NINT + k) * BOYS_NC;
+    const float* c = (const float*)tabL + k * BOYS_NC;
     float b1 = 0.0f, b2 = 0.0f;
 #pragma unroll
     for (int j = BOYS_NC - 1; j >= 1; --j) {
@@ -103,13 +115,13 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
 }
 
 // ---------------------------------------------------------------------------
-// Shell-pair data of one pair class (la >= lb), structure of arrays.
-// Pair-level arrays are [npair]; primitive-pair arrays are [nprim2][stride]
-// (primitive index major) so that lanes holding consecutive pairs read
-// consecutive addresses.  Pairs are sorted by Schwarz factor, descending.
+// Shell-pair data of one pair class (la >= lb).  Pair-level arrays are
+// [npair]; the primitive-pair data of a pair is one contiguous run of
+// records, so a lane fetches a primitive pair with a few wide loads (a wave
+// touches at most eight distinct ket pairs per step).
 // ---------------------------------------------------------------------------
 struct PairSet {
-    int npair, nprim2, stride, pad_;
+    int npair, nprim2, stride, pad_;  // stride: unused (kept for layout)
     const int* sa;   // first shell (angular momentum la)
     const int* sb;   // second shell
     const int* fa;   // first function of sa, counted from its molecule's first
@@ -118,15 +130,9 @@ struct PairSet {
     const double* ABy;
     const double* ABz;
     const double* Q;    // Schwarz factor of the pair (raw components)
-    const double* p;    // alpha + beta
-    const double* oo2p; // 1 / (2p)
-    const double* Px;   // (alpha A + beta B) / p
-    const double* Py;
-    const double* Pz;
-    const double* PAx;  // P - A
-    const double* PAy;
-    const double* PAz;
-    const double* K;    // c_a c_b exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p
+    // Primitive-pair records [npair][nprim2][10]: p, K, 1/(2p), Px, Py, Pz,
+    // PAx, PAy, PAz, 0 (one lane reads its record with five 16-byte loads).
+    const double* rec;  // K = c_a c_b exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p
 };
 
 // One molecule of a basis (a batch holds many): its shells and functions are

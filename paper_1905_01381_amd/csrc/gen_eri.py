@@ -134,10 +134,10 @@ class VRR:
                 f2 = sub(f1, i)
                 c = self.get(e, f2, m)
                 d = self.get(e, f2, m + 1)
-                terms.append(f"{lit(f1[i])} * (oo2q * {c} - rq2 * {d})")
+                terms.append(f"cq{f1[i]} * {c} - dq{f1[i]} * {d}")
             if e[i] > 0:
                 g = self.get(sub(e, i), f1, m + 1)
-                terms.append(f"{lit(e[i])} * oo2pq * {g}")
+                terms.append(f"cx{e[i]} * {g}")
         else:
             i = next(k for k in range(3) if e[k] > 0)
             e1 = sub(e, i)
@@ -149,7 +149,7 @@ class VRR:
                 e2 = sub(e1, i)
                 c = self.get(e2, f, m)
                 d = self.get(e2, f, m + 1)
-                terms.append(f"{lit(e1[i])} * (oo2p * {c} - rp2 * {d})")
+                terms.append(f"cp{e1[i]} * {c} - dp{e1[i]} * {d}")
         self.out(f"const {T_()} {nm} = " + " + ".join(terms) + ";")
         self.count += 1
         self.memo[key] = nm
@@ -174,20 +174,27 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
     L = la + lb + lc + ld
     T = T_()
     out("for (int kp = 0; kp < bra.nprim2; ++kp) {")
-    out(f"  const {T} p = bra.p[kp * bra.stride + ib];")
-    out(f"  const {T} Kab = bra.K[kp * bra.stride + ib];")
+    out("  const double2* br = (const double2*)(bra.rec + ((size_t)ib * bra.nprim2 + kp) * 10);")
+    out("  const double2 b0 = br[0];")
+    out(f"  const {T} p = b0.x;")
+    out(f"  const {T} Kab = b0.y;")
     out("  if (Kab == 0) continue;")
-    out(f"  const {T} oo2p = bra.oo2p[kp * bra.stride + ib];")
-    out(f"  const {T} Px = bra.Px[kp * bra.stride + ib], Py = bra.Py[kp * bra.stride + ib], Pz = bra.Pz[kp * bra.stride + ib];")
+    out("  const double2 b1 = br[1], b2 = br[2];")
+    out(f"  const {T} oo2p = b1.x;")
+    out(f"  const {T} Px = b1.y, Py = b2.x, Pz = b2.y;")
     if la + lb > 0:
-        out(f"  const {T} PAx = bra.PAx[kp * bra.stride + ib], PAy = bra.PAy[kp * bra.stride + ib], PAz = bra.PAz[kp * bra.stride + ib];")
+        out("  const double2 b3 = br[3], b4 = br[4];")
+        out(f"  const {T} PAx = b3.x, PAy = b3.y, PAz = b4.x;")
     out("  for (int kq = 0; kq < ket.nprim2; ++kq) {")
-    out(f"    const {T} q = ket.p[kq * ket.stride + jk];")
-    out(f"    const {T} Kcd = ket.K[kq * ket.stride + jk];")
-    out(f"    const {T} oo2q = ket.oo2p[kq * ket.stride + jk];")
-    out(f"    const {T} Qx = ket.Px[kq * ket.stride + jk], Qy = ket.Py[kq * ket.stride + jk], Qz = ket.Pz[kq * ket.stride + jk];")
+    out("    const double2* kr = (const double2*)(ket.rec + ((size_t)jk * ket.nprim2 + kq) * 10);")
+    out("    const double2 k0 = kr[0], k1 = kr[1], k2 = kr[2];")
+    out(f"    const {T} q = k0.x;")
+    out(f"    const {T} Kcd = k0.y;")
+    out(f"    const {T} oo2q = k1.x;")
+    out(f"    const {T} Qx = k1.y, Qy = k2.x, Qz = k2.y;")
     if lc + ld > 0:
-        out(f"    const {T} QCx = ket.PAx[kq * ket.stride + jk], QCy = ket.PAy[kq * ket.stride + jk], QCz = ket.PAz[kq * ket.stride + jk];")
+        out("    const double2 k3 = kr[3], k4 = kr[4];")
+        out(f"    const {T} QCx = k3.x, QCy = k3.y, QCz = k4.x;")
     out(f"    const {T} pq = p + q;")
     out(f"    const {T} rs = {'rsqrt_f64' if T == 'double' else 'rsqrt_f32'}(pq);")
     out(f"    const {T} inv = rs * rs;")
@@ -195,7 +202,7 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
     out(f"    const {T} rho = p * q * inv;")
     out(f"    const {T} T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
     out(f"    {T} F[{L + 1}];")
-    out(f"    {'boys_fp64' if T == 'double' else 'boys_fp32'}<{L}>(T, boys_tab, F);")
+    out(f"    {'boys_fp64_tab' if T == 'double' else 'boys_fp32_tab'}<{L}>(T, s_boys, F);")
     out(f"    const {T} pref = Kab * Kcd * rs;")
     for m in range(L + 1):
         out(f"    const {T} ss{m} = pref * F[{m}];")
@@ -207,6 +214,28 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
         if lc + ld > 0:
             out(f"    const {T} WQx = p * inv * PQx, WQy = p * inv * PQy, WQz = p * inv * PQz;")
             out(f"    const {T} rq2 = p * inv * oo2q;")
+        # recurrence coefficients premultiplied by the integer factors they
+        # take (k / 2p, k rho / 2p^2, k / 2(p+q), ...): every VRR node is then
+        # one multiply and a chain of fused multiply-adds
+        for k in range(1, la + lb):
+            out(f"    const {T} cp{k} = {lit(k)} * oo2p, dp{k} = {lit(k)} * rp2;")
+        for k in range(1, lc + ld):
+            out(f"    const {T} cq{k} = {lit(k)} * oo2q, dq{k} = {lit(k)} * rq2;")
+        for k in range(1, la + lb + 1 if lc + ld > 0 else 1):
+            out(f"    const {T} cx{k} = {lit(k)} * oo2pq;")
+
+
+def emit_boys_lds(o: Emitter, L: int, f32: bool):
+    """Kernel prologue: copy the Boys coefficients of order L into LDS (FP32
+    ones for the FP32 path below L = 6, FP64 ones otherwise)."""
+    if f32 and L < 6:
+        o("  __shared__ float s_boys[BOYS_TAB_L];")
+        o(f"  {{ const float* src = (const float*)(boys_tab + BOYS_TAB_DOUBLES) + {L} * BOYS_TAB_L;")
+    else:
+        o("  __shared__ double s_boys[BOYS_TAB_L];")
+        o(f"  {{ const double* src = boys_tab + {L} * BOYS_TAB_L;")
+    o("    for (int i = threadIdx.x; i < BOYS_TAB_L; i += blockDim.x) s_boys[i] = src[i]; }")
+    o("  __syncthreads();")
 
 
 def emit_eri_body(out: Emitter, la, lb, lc, ld, prec="double"):
@@ -371,28 +400,92 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
 # --------------------------------------------------------------------------
 # Staged variant for high angular momentum: the contracted intermediates do
 # not fit one lane's registers, so the VRR runs in passes over subsets of
-# <= STAGE_CAP targets (each pass re-runs the primitive loop for its own
-# subset), and the contracted [e0|f0], the bra-transferred (ab|f] and the
+# targets (each pass re-runs the primitive loop for its own subset), and the contracted [e0|f0], the bra-transferred (ab|f] and the
 # final (ab|cd) go through a per-wave global stage laid out [index][lane]
 # (coalesced, private to the wave).
 # --------------------------------------------------------------------------
-STAGE_CAP = 48
+
+# Per-class staging: (targets per pass, waves per SIMD the kernel is
+# compiled for).  Smaller passes re-run more of the VRR but free registers
+# for a second wave per SIMD, which one wave alone cannot keep the FP64
+# pipeline busy without (measured per class on MI355X).
+STAGE_CFG = {
+    (2, 1, 1, 1): (24, 2),
+    (2, 1, 2, 1): (24, 2),
+    (2, 2, 1, 1): (24, 2),
+    (2, 2, 2, 0): (24, 2),
+    (2, 2, 2, 1): (24, 2),
+    (2, 2, 2, 2): (48, 1),
+}
 
 
 def is_staged(la, lb, lc, ld):
+    return (la, lb, lc, ld) in STAGE_CFG
+
+
+def stage_cap(la, lb, lc, ld):
+    return STAGE_CFG[(la, lb, lc, ld)][0]
+
+
+def waves_per_simd(la, lb, lc, ld):
+    return STAGE_CFG[(la, lb, lc, ld)][1] if is_staged(la, lb, lc, ld) else 1
+
+
+def _vrr_ancestors(la, lb, lc, ld):
+    """For every contraction target [e0|f0]: the VRR nodes it needs and the
+    operation count of each node."""
+    L = la + lb + lc + ld
     es, fs = targets(la, lb, lc, ld)
-    nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-    return len(es) * len(fs) > 96 or nv > 150
+    em = Emitter("")
+    full = VRR(em, L)
+    for e in es:
+        for f in fs:
+            full.get(e, f, 0)
+    ops = {}
+    for line in em.lines:
+        lhs, rhs = line.split("=", 1)
+        ops[lhs.split()[-1]] = rhs.count("*") + rhs.count("+") + rhs.count(" - ")
+    keys = sorted(full.memo)
+    col = {k: i for i, k in enumerate(keys)}
+    w = [ops.get(full.memo[k], 0) for k in keys]
+    anc = {}
+    for e in es:
+        for f in fs:
+            v = VRR(Emitter(""), L)
+            v.get(e, f, 0)
+            anc[(e, f)] = sorted(col[k] for k in v.memo)
+    return anc, w
 
 
-def stage_subsets(la, lb, lc, ld, cap=STAGE_CAP):
+def stage_subsets(la, lb, lc, ld, cap=None):
+    """Split the targets into passes of <= cap.  Every pass re-runs the VRR
+    for the ancestors of its own targets, so passes are filled greedily: seed
+    with the most expensive remaining target, then repeatedly add the target
+    that brings the fewest new VRR operations."""
+    import numpy as np
+    if cap is None:
+        cap = stage_cap(la, lb, lc, ld)
+    anc, w = _vrr_ancestors(la, lb, lc, ld)
+    tg = sorted(anc)
+    M = np.zeros((len(tg), len(w)), dtype=bool)
+    for r, t in enumerate(tg):
+        M[r, anc[t]] = True
+    W = np.asarray(w, dtype=np.int64)
+    cost = M.astype(np.int64) @ W
+    left = np.ones(len(tg), dtype=bool)
     out = []
-    for le in range(la, la + lb + 1):
-        for lf in range(lc, lc + ld + 1):
-            E, F = comps(le), comps(lf)
-            per = max(1, cap // len(F))
-            for k in range(0, len(E), per):
-                out.append([(e, f) for e in E[k:k + per] for f in F])
+    while left.any():
+        seed = int(np.flatnonzero(left)[np.argmax(cost[left])])
+        cur, have = [seed], M[seed].copy()
+        left[seed] = False
+        while len(cur) < cap and left.any():
+            idx = np.flatnonzero(left)
+            extra = (M[idx] & ~have).astype(np.int64) @ W
+            pick = int(idx[np.argmin(extra)])
+            cur.append(pick)
+            have |= M[pick]
+            left[pick] = False
+        out.append([tg[r] for r in sorted(cur)])
     return out
 
 
@@ -620,10 +713,13 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     same_ab = int(la == lb)
     same_cd = int(lc == ld)
     same_cls = int((la, lb) == (lc, ld))
-    o(f"__global__ __launch_bounds__(64) void {kname}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab)")
+    wpe = waves_per_simd(la, lb, lc, ld)
+    lb_ = f"__launch_bounds__(64, {wpe})" if wpe > 1 else "__launch_bounds__(64)"
+    o(f"__global__ {lb_} void {kname}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab)")
     o("{")
     if f32:
         o("  if (dg.mode != 1) return;")
+    emit_boys_lds(o, L, f32)
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
     if staged:
@@ -715,6 +811,7 @@ def gen(lmax: int) -> dict:
         emit_eri_body(body2, la, lb, lc, ld)
         o(f"__global__ __launch_bounds__(64) void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab)")
         o("{")
+        emit_boys_lds(o, la + lb + lc + ld, False)
         o("  const int t = blockIdx.x * blockDim.x + threadIdx.x;")
         o("  if (t >= nq) return;")
         o("  const int ib = qlist[2 * t], jk = qlist[2 * t + 1];")

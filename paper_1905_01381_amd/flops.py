@@ -48,6 +48,8 @@ def per_quartet(la, lb, lc, ld, nprim2_bra=9, nprim2_ket=9, nJ=1, nK=1) -> float
     setup = SETUP["base"] + (L + 1)
     if L > 0:
         setup += 1 + (8 if la + lb > 0 else 0) + (8 if lc + ld > 0 else 0)
+        # recurrence coefficients premultiplied by their integer factors
+        setup += 2 * max(la + lb - 1, 0) + 2 * max(lc + ld - 1, 0) + (la + lb if lc + ld > 0 else 0)
     prim = setup + boys_ops(L) + vrr_ops + len(es) * len(fs)
     # horizontal transfers: 2 ops per emitted node
     em2 = gen_eri.Emitter("")
