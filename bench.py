@@ -25,6 +25,12 @@ Other workloads (one JSON line each, same top-level keys; not the headline):
   --workload c5   real-time Magnus-2 steps (EM2) on the 60-atom Z=1 workload:
                   time per step and per Fock build after an RHF ground state
                   and a delta kick; --atoms scales the molecule
+  --workload c5l  the learned-midpoint protocol on the same recipe (default
+                  12 atoms): plain self-consistent midpoint for --rt-steps
+                  steps; the learned run records the first --rt-train steps,
+                  trains the network on the GPU, then proposes midpoints;
+                  the ablation zeroes the network.  Reports builds/step,
+                  dipole error vs plain and energy drift
 """
 from __future__ import annotations
 
@@ -54,9 +60,12 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l"])
     ap.add_argument("--atoms", type=int, default=0, help="c3/c5: atoms (0 = the full workload)")
     ap.add_argument("--nmol", type=int, default=16, help="c4: number of molecules (smallest first)")
+    ap.add_argument("--rt-steps", type=int, default=2000, help="c5l: trajectory length")
+    ap.add_argument("--rt-train", type=int, default=500, help="c5l: steps recorded for training")
+    ap.add_argument("--epochs", type=int, default=200, help="c5l: training epochs")
     return ap.parse_args()
 
 
@@ -177,17 +186,14 @@ def bench_c4(a, torch, cq, inputs):
     }
 
 
-def bench_c5(a, torch, cq, inputs):
-    """EM2 real-time steps on the Z=1 lattice workload after an RHF ground
-    state and a delta kick along z."""
+def _c5_state(a, torch, cq, inputs, natom):
     from paper_1905_01381_amd import scf
-    natom = a.atoms or 60
     w = inputs.c5(natom=natom)
     gb = cq.Basis.from_molecule(w.mol)
     t0 = time.perf_counter()
     res = scf.rhf(gb, w.mol, natom // 2)
-    t_scf = time.perf_counter() - t0
-    _log(f"c5: {natom} atoms, nbf {gb.nbf}; RHF E = {res.energy:.8f} in {res.iterations} iterations ({t_scf:.1f} s)")
+    _log(f"{natom} atoms, nbf {gb.nbf}; RHF E = {res.energy:.8f} in {res.iterations} iterations "
+         f"({time.perf_counter() - t0:.1f} s)")
     Dz = gb.one_electron("dipole", direction=2).cpu().numpy()
     X = res.X
     Sh = res.S @ X
@@ -196,7 +202,92 @@ def bench_c5(a, torch, cq, inputs):
     Uk = (U * np.exp(-1j * 1e-4 * lam)) @ U.T
     P0 = Uk @ Po @ Uk.conj().T
     d = lambda m: torch.from_numpy(np.ascontiguousarray(m)).cuda()
-    rt = cq.RT(gb, d(res.h), d(X), d(Dz), d(P0), 0.05, cq.RT_EM2)
+    return gb, res, (d(res.h), d(X), d(Dz), d(P0))
+
+
+def _rt_steps(r, n, label, chunk=100):
+    """r.step(n) in chunks, with one progress line per chunk."""
+    Es, mus, nbs = [], [], []
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        E, mu, nb = r.step(k, energy=True)
+        Es.append(E)
+        mus.append(mu)
+        nbs.append(nb)
+        done += k
+        _log(f"{label}: {done}/{n} steps, {np.concatenate(nbs).mean():.3f} builds/step")
+    return np.concatenate(Es), np.concatenate(mus), np.concatenate(nbs)
+
+
+def bench_c5l(a, torch, cq, inputs):
+    """Learned midpoint proposal vs the plain self-consistent midpoint
+    corrector on the C5 recipe (reduced molecule), same initial state."""
+    natom = a.atoms or 12
+    gb, res, args = _c5_state(a, torch, cq, inputs, natom)
+    dt, nt, nall = 0.05, a.rt_train, a.rt_steps
+    t0 = time.perf_counter()
+    plain = cq.RT(gb, *args, dt, cq.RT_MIDPOINT)
+    plain.set_params(sc_tol=1e-10, max_iter=40)
+    E_p, mu_p, nb_p = _rt_steps(plain, nall, "plain midpoint")
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    _log(f"plain midpoint: {nall} steps, {nb_p.mean():.3f} builds/step, {t_plain:.1f} s")
+
+    def learned(epochs, zero):
+        r = cq.RT(gb, *args, dt, cq.RT_MIDPOINT)
+        r.set_params(sc_tol=1e-10, max_iter=40, accept_tol=1e-6)
+        r.record(True, 4096, 1)
+        t0 = time.perf_counter()
+        E1, mu1, nb1 = _rt_steps(r, nt, "recording")
+        r.record(False)
+        t1 = time.perf_counter()
+        loss = r.train(epochs=epochs, lr=3e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        if zero:
+            r.weights(np.zeros(354, np.float32))
+        r.set_mode(cq.RT_LEARNED)
+        t2 = time.perf_counter()
+        E2, mu2, nb2 = _rt_steps(r, nall - nt, "ablation" if zero else "learned")
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t2
+        st = r.stats()
+        r.close()
+        return (np.concatenate([E1, E2]), np.concatenate([mu1, mu2]), np.concatenate([nb1, nb2]), loss, t_train,
+                t_run, st, t1 - t0)
+
+    E_l, mu_l, nb_l, loss, t_train, t_run, st, t_rec = learned(a.epochs, False)
+    _log(f"learned: loss {loss:.3e}, train {t_train:.2f} s, {nb_l[nt:].mean():.3f} builds/step after training")
+    E_z, mu_z, nb_z, _, _, t_run_z, st_z, _ = learned(0, True)
+    _log(f"ablation: {nb_z[nt:].mean():.3f} builds/step")
+    err = float(np.abs(mu_l - mu_p).max())
+    err_z = float(np.abs(mu_z - mu_p).max())
+    per_step_plain = t_plain / nall
+    return {
+        "metric": "RT-TDSCF J/K builds per step: learned midpoint proposal vs plain self-consistent midpoint",
+        "value": float(nb_l[nt:].mean()), "unit": "builds/step", "n_gpus": 1, "steps": nall - nt, "warmup": nt,
+        "ms_per_step": t_run / (nall - nt) * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (MLP f32)", "data": "synthetic",
+        "config": {"workload": f"RT-TDSCF learned midpoint: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, "
+                               f"{natom // 2} doubly occupied; kick 1e-4 along z; dt 0.05; {nall} steps, "
+                               f"network trained on the first {nt}", "nbf": gb.nbf},
+        "plain_builds_per_step": float(nb_p[nt:].mean()),
+        "ablation_builds_per_step": float(nb_z[nt:].mean()),
+        "max_dipole_diff_learned_vs_plain": err, "max_dipole_diff_ablation_vs_plain": err_z,
+        "energy_drift_plain": float(np.abs(E_p - E_p[0]).max()),
+        "energy_drift_learned": float(np.abs(E_l - E_l[0]).max()),
+        "ms_per_step_plain": per_step_plain * 1e3, "ms_per_step_ablation": t_run_z / (nall - nt) * 1e3,
+        "train_loss": loss, "train_s": t_train, "record_s": t_rec, "stats_learned": st, "stats_ablation": st_z,
+    }
+
+
+def bench_c5(a, torch, cq, inputs):
+    """EM2 real-time steps on the Z=1 lattice workload after an RHF ground
+    state and a delta kick along z."""
+    natom = a.atoms or 60
+    gb, res, args = _c5_state(a, torch, cq, inputs, natom)
+    rt = cq.RT(gb, *args, 0.05, cq.RT_EM2)
     if a.warmup > 0:
         rt.step(a.warmup, dipole=False)
     torch.cuda.synchronize()
@@ -283,7 +374,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if a.workload != "c2":
-        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[a.workload]
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5l": bench_c5l}[a.workload]
         print(json.dumps(fn(a, torch, cq, inputs)), flush=True)
         return
     w, gb, P2 = build_inputs(torch, cq, inputs)

@@ -291,40 +291,89 @@ __global__ void k_mlp_record(const double2* __restrict__ p0, const double2* __re
     Y[2LL * s + 1] = (float)((m.y - q.y) / out_scale);
 }
 
-// loss and gradients of 1/(2N) sum |y - t|^2 over N samples; per-block LDS
-// accumulation, one atomic per parameter per block
-__global__ void k_mlp_backward(const float* __restrict__ X, const float* __restrict__ Y, int ns, const float* __restrict__ w,
-                               float* __restrict__ grad, float* __restrict__ loss)
+// loss and gradients of 1/(2N) sum |y - t|^2 over N samples.  A block
+// takes chunks of kBwdChunk samples: each thread runs one sample forward and
+// back and leaves x, h, e = dL/dy and dz = dL/dz1 in LDS; then each thread
+// owns up to three parameters and sums their gradient over the chunk from
+// LDS (no atomics inside the block), and finally adds its totals to the
+// global gradient with one atomic per parameter per block.
+constexpr int kBwdChunk = 128;
+constexpr int kBwdOwn = (kMlpParams + kBwdChunk - 1) / kBwdChunk;  // parameters per thread
+
+__global__ __launch_bounds__(kBwdChunk) void k_mlp_backward(const float* __restrict__ X, const float* __restrict__ Y,
+                                                           int ns, const float* __restrict__ w,
+                                                           float* __restrict__ grad, float* __restrict__ loss)
 {
-    __shared__ float g[kMlpParams + 1];
-    for (int i = threadIdx.x; i < kMlpParams + 1; i += blockDim.x) g[i] = 0.0f;
-    __syncthreads();
+    __shared__ float sx[kBwdChunk][kMlpIn + 1];
+    __shared__ float sh[kBwdChunk][kMlpHid + 1];
+    __shared__ float sdz[kBwdChunk][kMlpHid + 1];
+    __shared__ float se[kBwdChunk][kMlpOut];
+    __shared__ float sl[kBwdChunk];
     const MlpW* W = (const MlpW*)w;
     const float inv = 1.0f / (float)ns;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x) {
-        float x[kMlpIn], h[kMlpHid], y[kMlpOut];
-        for (int i = 0; i < kMlpIn; ++i) x[i] = X[(long long)s * kMlpIn + i];
-        mlp_fwd(w, x, h, y);
-        float e[kMlpOut];
-        for (int o = 0; o < kMlpOut; ++o) e[o] = (y[o] - Y[2LL * s + o]) * inv;
-        atomicAdd(&g[kMlpParams], 0.5f * (e[0] * e[0] + e[1] * e[1]) * (float)ns);
-        const int oW1 = 0, ob1 = kMlpHid * kMlpIn, oW2 = ob1 + kMlpHid, ob2 = oW2 + kMlpOut * kMlpHid;
-        for (int o = 0; o < kMlpOut; ++o) {
-            atomicAdd(&g[ob2 + o], e[o]);
-            for (int k = 0; k < kMlpHid; ++k) atomicAdd(&g[oW2 + o * kMlpHid + k], e[o] * h[k]);
+    const int t = threadIdx.x;
+    constexpr int oW1 = 0, ob1 = kMlpHid * kMlpIn, oW2 = ob1 + kMlpHid, ob2 = oW2 + kMlpOut * kMlpHid;
+    float acc[kBwdOwn];
+#pragma unroll
+    for (int q = 0; q < kBwdOwn; ++q) acc[q] = 0.0f;
+    float lsum = 0.0f;
+    for (int base = blockIdx.x * kBwdChunk; base < ns; base += gridDim.x * kBwdChunk) {
+        const int s = base + t;
+        const int nc = min(kBwdChunk, ns - base);
+        if (s < ns) {
+            float x[kMlpIn], h[kMlpHid], y[kMlpOut], e[kMlpOut];
+            for (int i = 0; i < kMlpIn; ++i) x[i] = X[(long long)s * kMlpIn + i];
+            mlp_fwd(w, x, h, y);
+            for (int o = 0; o < kMlpOut; ++o) e[o] = (y[o] - Y[2LL * s + o]) * inv;
+            lsum += 0.5f * (e[0] * e[0] + e[1] * e[1]) * (float)ns;
+            for (int i = 0; i < kMlpIn; ++i) sx[t][i] = x[i];
+            for (int o = 0; o < kMlpOut; ++o) se[t][o] = e[o];
+            for (int k = 0; k < kMlpHid; ++k) {
+                float dh = 0.0f;
+                for (int o = 0; o < kMlpOut; ++o) dh = fmaf(W->W2[o * kMlpHid + k], e[o], dh);
+                sh[t][k] = h[k];
+                sdz[t][k] = dh * (1.0f - h[k] * h[k]);
+            }
         }
-        for (int k = 0; k < kMlpHid; ++k) {
-            float dh = 0.0f;
-            for (int o = 0; o < kMlpOut; ++o) dh = fmaf(W->W2[o * kMlpHid + k], e[o], dh);
-            const float dz = dh * (1.0f - h[k] * h[k]);
-            atomicAdd(&g[ob1 + k], dz);
-            for (int i = 0; i < kMlpIn; ++i) atomicAdd(&g[oW1 + k * kMlpIn + i], dz * x[i]);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBwdOwn; ++q) {
+            const int pidx = t + q * kBwdChunk;
+            if (pidx >= kMlpParams) continue;
+            float g = 0.0f;
+            if (pidx < ob1) {
+                const int k = pidx / kMlpIn, i = pidx % kMlpIn;
+                for (int j = 0; j < nc; ++j) g = fmaf(sdz[j][k], sx[j][i], g);
+            } else if (pidx < oW2) {
+                const int k = pidx - ob1;
+                for (int j = 0; j < nc; ++j) g += sdz[j][k];
+            } else if (pidx < ob2) {
+                const int o = (pidx - oW2) / kMlpHid, k = (pidx - oW2) % kMlpHid;
+                for (int j = 0; j < nc; ++j) g = fmaf(se[j][o], sh[j][k], g);
+            } else {
+                const int o = pidx - ob2;
+                for (int j = 0; j < nc; ++j) g += se[j][o];
+            }
+            acc[q] += g;
         }
+        __syncthreads();
     }
+#pragma unroll
+    for (int q = 0; q < kBwdOwn; ++q) {
+        const int pidx = t + q * kBwdChunk;
+        if (pidx < kMlpParams) atomicAdd(&grad[pidx], acc[q]);
+    }
+    sl[t] = lsum;
     __syncthreads();
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) atomicAdd(&grad[i], g[i]);
-    if (threadIdx.x == 0) atomicAdd(loss, g[kMlpParams]);
+    for (int h2 = kBwdChunk / 2; h2 > 0; h2 >>= 1) {
+        if (t < h2) sl[t] += sl[t + h2];
+        __syncthreads();
+    }
+    if (t == 0) atomicAdd(loss, sl[0]);
 }
+
+// blocks for the backward pass over ns samples (each loops over chunks)
+static inline unsigned bwd_grid(int ns) { return (unsigned)std::max(1, std::min(64, (ns + kBwdChunk - 1) / kBwdChunk)); }
 
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v, int n,
                        float lr, float b1, float b2, float eps, int step)
@@ -861,7 +910,7 @@ extern "C" cq_status cq_rt_train(cq_rt r, int epochs, float lr, float* loss)
         for (size_t k = 0; k < r->recX.size(); ++k) {
             hipLaunchKernelGGL(k_fill_f, dim3(2), dim3(256), 0, r->stream, r->gw, kMlpParams, 0.0f);
             hipLaunchKernelGGL(k_fill_f, dim3(1), dim3(64), 0, r->stream, r->lossd, 1, 0.0f);
-            hipLaunchKernelGGL(k_mlp_backward, dim3((r->rec_per_step + 255) / 256), dim3(256), 0, r->stream,
+            hipLaunchKernelGGL(k_mlp_backward, dim3(bwd_grid(r->rec_per_step)), dim3(kBwdChunk), 0, r->stream,
                                r->recX[k], r->recY[k], r->rec_per_step, r->w, r->gw, r->lossd);
             r->adam_step++;
             hipLaunchKernelGGL(k_adam, dim3(2), dim3(256), 0, r->stream, r->w, r->gw, r->am, r->av, kMlpParams, lr, 0.9f,
@@ -910,7 +959,7 @@ extern "C" cq_status cq_mlp_eval(const float* w354, const float* X, const float*
     if (!w354 || !X || !Y || ns < 1 || !grad || !loss) return cq_internal_fail(CQ_EINVAL, "bad arguments");
     hipLaunchKernelGGL(k_fill_f, dim3(2), dim3(256), 0, stream, grad, kMlpParams, 0.0f);
     hipLaunchKernelGGL(k_fill_f, dim3(1), dim3(64), 0, stream, loss, 1, 0.0f);
-    hipLaunchKernelGGL(k_mlp_backward, dim3((ns + 255) / 256), dim3(256), 0, stream, X, Y, ns, w354, grad, loss);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(bwd_grid(ns)), dim3(kBwdChunk), 0, stream, X, Y, ns, w354, grad, loss);
     RTCHK(hipGetLastError());
     return CQ_OK;
 }
