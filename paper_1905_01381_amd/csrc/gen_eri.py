@@ -388,10 +388,14 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
             out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fc + {k}, ks), s); }}")
+    # K'_bd does not depend on c: it accumulates per lane in LDS over the
+    # task's c range and is flushed once per task (kbd_flush)
     for j in range(nb):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
-            out(f"    if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), {s});")
+            out(f"    {{ const {T_()} s = {s};")
+            out(f"      if (dg.kbd_direct) {{ if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
+            out(f"      else s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane] += s; }}")
     out("  }")
     out("}")
 
@@ -457,14 +461,37 @@ def _vrr_ancestors(la, lb, lc, ld):
     return anc, w
 
 
+PASS_OVERHEAD = 150
+
+
+def _pass_cost(la, lb, lc, ld, subsets):
+    """VRR operations of a pass plan (each pass re-runs its ancestors)."""
+    anc, w = _vrr_ancestors(la, lb, lc, ld)
+    return sum(sum(w[k] for k in set().union(*(anc[t] for t in sub))) for sub in subsets)
+
+
 def stage_subsets(la, lb, lc, ld, cap=None):
-    """Split the targets into passes of <= cap.  Every pass re-runs the VRR
-    for the ancestors of its own targets, so passes are filled greedily: seed
-    with the most expensive remaining target, then repeatedly add the target
-    that brings the fewest new VRR operations."""
-    import numpy as np
+    """Split the targets into passes of <= cap targets; every pass re-runs
+    the VRR for the ancestors of its own targets.  Two plans are costed by
+    the VRR operations they re-run and the cheaper is kept: passes over a
+    few bra targets e with every ket target f (the recursion builds f on top
+    of a fixed e, so those share most ancestors), and greedy filling (seed
+    with the most expensive remaining target, then add the target that
+    brings the fewest new operations)."""
     if cap is None:
         cap = stage_cap(la, lb, lc, ld)
+    es, fs = targets(la, lb, lc, ld)
+    plans = [_greedy_subsets(la, lb, lc, ld, cap)]
+    k = cap // len(fs)
+    if k >= 1:
+        plans.append([[(e, f) for e in es[i:i + k] for f in fs] for i in range(0, len(es), k)])
+    # each pass also repeats the primitive setup, the Boys function and the
+    # primitive-pair loads: about PASS_OVERHEAD operations per primitive
+    return min(plans, key=lambda pl: (_pass_cost(la, lb, lc, ld, pl) + PASS_OVERHEAD * len(pl), len(pl)))
+
+
+def _greedy_subsets(la, lb, lc, ld, cap):
+    import numpy as np
     anc, w = _vrr_ancestors(la, lb, lc, ld)
     tg = sorted(anc)
     M = np.zeros((len(tg), len(w)), dtype=bool)
@@ -685,6 +712,27 @@ HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 // shell quartet) with Coulomb/exchange digestion."""
 
 
+def kbd_size(la, lb, lc, ld):
+    """K'_bd elements per lane and density held in LDS (unstaged classes)."""
+    return 0 if is_staged(la, lb, lc, ld) else ncart(lb) * ncart(ld)
+
+
+def emit_kbd_flush(o: Emitter, lb, ld):
+    nb, nd = ncart(lb), ncart(ld)
+    o("    if (!dg.kbd_direct) {")
+    o("      if (rowv && dval && fdv >= 0) {")
+    o("        for (int m = 0; m < dg.nX; ++m) {")
+    o("          const int ks = dg.kslot[m];")
+    o("          if (ks < 0) continue;")
+    for j in range(nb):
+        for l in range(nd):
+            o(f"          {{ const double s = s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane];")
+            o(f"            if (s != 0.0) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
+    o("        }")
+    o("      }")
+    o("    }")
+
+
 def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     """One J/K kernel of a class in one precision.  Both kernels of a class
     walk the same tasks and take the same per-step routing decision; each
@@ -720,6 +768,9 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     if f32:
         o("  if (dg.mode != 1) return;")
     emit_boys_lds(o, L, f32)
+    kbd = kbd_size(la, lb, lc, ld)
+    if kbd:
+        o("  extern __shared__ double s_kbd[];  // [kbd][nX][lane], sized at launch")
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
     if staged:
@@ -743,6 +794,10 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     if lb > 0:
         o(f"    const {t} ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
     o("    const int c_lo = tk.w, c_hi = tk2.w;")
+    if kbd:
+        o(f"    if (!dg.kbd_direct)")
+        o(f"      for (int t = 0; t < {kbd} * dg.nX; ++t) s_kbd[t * 64 + lane] = 0.0;")
+        o("    int fdv = -1;  // first function of d (valid once a step with this d ran)")
     o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
     o("      const int c = tm.shl_c[c_idx];")
     o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
@@ -751,6 +806,8 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
     o(f"      const int jk = mc.ppos[spair(mc, c, colv ? d : {'c' if same_cd else 'd'})];")
     o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
+    if kbd:
+        o("      if (colv) fdv = fd;")
     o("      const bool valid = active;")
     o("      double bnd = 0.0;")
     o("      if (dg.mode != 0 || dg.skip > 0.0) bnd = quartet_bound(mc, bra.Q[ib], ket.Q[jk], a, b, c, d);")
@@ -780,6 +837,8 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     dig.lines = ["  " + x if x else x for x in dig.lines]
     o(dig.text())
     o("    }")
+    if kbd:
+        emit_kbd_flush(o, lb, ld)
     o("  }")
     if staged:
         o("#undef STL")
@@ -841,13 +900,13 @@ def gen(lmax: int) -> dict:
         o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
     # dispatch tables
     o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int kbd; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {kbd_size(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)

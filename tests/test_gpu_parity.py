@@ -128,6 +128,26 @@ def test_multi_density_sym_antisym_spd(spd_case, torch_cuda):
     assert np.abs(K[1] + K[1].T).max() < 1e-13 * np.abs(K[1]).max()
 
 
+def test_sixteen_densities_mixed_symmetry(spd_case, torch_cuda):
+    """The maximum number of densities per build (16, mixed symmetric and
+    antisymmetric): the exchange partial sums that do not depend on the ket
+    shell c are kept per lane in LDS over a task, except where 16 slots of
+    them do not fit (the (pp|pp) class), which adds them straight to K'."""
+    torch = torch_cuda
+    w, ob, gb, P = spd_case
+    rng = np.random.default_rng(17)
+    sym = [1] + [1 if k % 3 else -1 for k in range(1, 16)]
+    mats = [P] + [inputs.random_symmetric(gb.nbf, rng, sym[k]) for k in range(1, 16)]
+    J, K = _jk_gpu(torch, gb, mats, sym, want_j=[x == 1 for x in sym])
+    Jr, Kr = ob.jk(np.stack(mats))
+    for m in range(16):
+        if sym[m] == 1:
+            assert rel_err(J[m], Jr[m]) < TOL_JK, m
+        else:
+            assert J[m] is None
+        assert rel_err(K[m], Kr[m]) < TOL_JK, m
+
+
 def test_tiles_span_rows_and_ragged_tail(torch_cuda):
     """12 atoms of 2s1p: rows of up to 5 tiles of 64 with ragged ends."""
     torch = torch_cuda
