@@ -46,7 +46,11 @@ def _fresh(src: str, obj: str) -> bool:
     if not os.path.exists(obj):
         return False
     t = os.path.getmtime(obj)
-    return all(os.path.getmtime(x) <= t for x in [src, *_headers()])
+    deps = _headers()
+    if os.path.basename(src).startswith("eri_"):
+        # generated class kernels include eri_common.hpp only, not the registry
+        deps = [d for d in deps if not d.startswith(GEN)]
+    return all(os.path.getmtime(x) <= t for x in [src, *deps])
 
 
 def _compile(src: str, extra: list[str], incremental: bool = False) -> tuple[str, str]:

@@ -194,7 +194,7 @@ struct Digest {
     int stage_blocks;     // waves that own a stage region (grid limit of staged classes)
     double* stage;        // per-wave private stage, [stage_blocks][class stage size][64]
     int mode;             // 0: FP64 everywhere; 1: precision-routed
-    int kbd_direct;       // 1: K'_bd partial sums go straight to K' (no LDS room)
+    int acc_direct;       // 1: task-invariant partial sums go straight to J'/K' (no LDS room)
     double fp32_below;    // routed mode: a wave step whose largest bound is below this runs in FP32
     unsigned long long* counts;  // [3]: quartets evaluated in FP64, in FP32, skipped by screening
 };

@@ -389,12 +389,12 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
             s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
             out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fc + {k}, ks), s); }}")
     # K'_bd does not depend on c: it accumulates per lane in LDS over the
-    # task's c range and is flushed once per task (kbd_flush)
+    # task's c range and is flushed once per task (acc_flush)
     for j in range(nb):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
             out(f"    {{ const {T_()} s = {s};")
-            out(f"      if (dg.kbd_direct) {{ if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
+            out(f"      if (dg.acc_direct) {{ if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
             out(f"      else s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane] += s; }}")
     out("  }")
     out("}")
@@ -712,23 +712,33 @@ HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 // shell quartet) with Coulomb/exchange digestion."""
 
 
-def kbd_size(la, lb, lc, ld):
-    """K'_bd elements per lane and density held in LDS (unstaged classes)."""
-    return 0 if is_staged(la, lb, lc, ld) else ncart(lb) * ncart(ld)
+def acc_doubles(la, lb, lc, ld):
+    """LDS doubles per density slot for the task accumulator of K'_bd (one
+    per lane and element; unstaged classes only).  K'_ad and J'_ab are
+    task-invariant too, but they take one atomic per eight lanes only and
+    accumulating them in LDS measured no faster."""
+    return 0 if is_staged(la, lb, lc, ld) else 64 * ncart(lb) * ncart(ld)
 
 
-def emit_kbd_flush(o: Emitter, lb, ld):
+def emit_acc_zero(o: Emitter, la, lb, lc, ld):
+    """Each accumulator entry is zeroed, summed and flushed by its own lane,
+    so no cross-lane ordering is needed."""
+    kbd = acc_doubles(la, lb, lc, ld) // 64
+    o("    if (!dg.acc_direct)")
+    o(f"      for (int t = 0; t < {kbd} * dg.nX; ++t) s_kbd[t * 64 + lane] = 0.0;")
+
+
+def emit_acc_flush(o: Emitter, la, lb, ld):
+    """Once per task: add the LDS accumulator to K'."""
     nb, nd = ncart(lb), ncart(ld)
-    o("    if (!dg.kbd_direct) {")
-    o("      if (rowv && dval && fdv >= 0) {")
-    o("        for (int m = 0; m < dg.nX; ++m) {")
-    o("          const int ks = dg.kslot[m];")
-    o("          if (ks < 0) continue;")
+    o("    if (!dg.acc_direct && rowv && dval && fdv >= 0) {")
+    o("      for (int m = 0; m < dg.nX; ++m) {")
+    o("        const int ks = dg.kslot[m];")
+    o("        if (ks < 0) continue;")
     for j in range(nb):
         for l in range(nd):
-            o(f"          {{ const double s = s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane];")
-            o(f"            if (s != 0.0) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
-    o("        }")
+            o(f"        {{ const double s = s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane];")
+            o(f"          if (s != 0.0) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
     o("      }")
     o("    }")
 
@@ -768,9 +778,9 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     if f32:
         o("  if (dg.mode != 1) return;")
     emit_boys_lds(o, L, f32)
-    kbd = kbd_size(la, lb, lc, ld)
+    kbd = acc_doubles(la, lb, lc, ld)
     if kbd:
-        o("  extern __shared__ double s_kbd[];  // [kbd][nX][lane], sized at launch")
+        o("  extern __shared__ double s_kbd[];  // K'_bd accumulator [kbd][nX][64 lanes], sized at launch")
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
     if staged:
@@ -795,8 +805,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o(f"    const {t} ABx = bra.ABx[ib], ABy = bra.ABy[ib], ABz = bra.ABz[ib];")
     o("    const int c_lo = tk.w, c_hi = tk2.w;")
     if kbd:
-        o(f"    if (!dg.kbd_direct)")
-        o(f"      for (int t = 0; t < {kbd} * dg.nX; ++t) s_kbd[t * 64 + lane] = 0.0;")
+        emit_acc_zero(o, la, lb, lc, ld)
         o("    int fdv = -1;  // first function of d (valid once a step with this d ran)")
     o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
     o("      const int c = tm.shl_c[c_idx];")
@@ -838,7 +847,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     o(dig.text())
     o("    }")
     if kbd:
-        emit_kbd_flush(o, lb, ld)
+        emit_acc_flush(o, la, lb, ld)
     o("  }")
     if staged:
         o("#undef STL")
@@ -900,13 +909,13 @@ def gen(lmax: int) -> dict:
         o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
     # dispatch tables
     o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int kbd; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {kbd_size(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)
