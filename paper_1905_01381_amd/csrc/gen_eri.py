@@ -650,10 +650,14 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
     return nodes
 
 
+DIGEST_VALUES = 36  # integrals a staged digestion group keeps in registers
+
+
 def emit_staged_digest(out: Emitter, la, lb, lc, ld):
-    """Digestion reading (ab|cd) from the stage: for every output element the
-    contributing integrals are loaded once, then the loop over densities
-    reuses them (lane reductions and flush as in emit_digest)."""
+    """Digestion reading (ab|cd) from the stage: for every group of output
+    elements the contributing integrals are loaded once, then the loop over
+    densities gathers each X element once for the whole group (lane
+    reductions and flush as in emit_digest)."""
     na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
     _, _, V0, _ = stage_layout(la, lb, lc, ld)
 
@@ -677,23 +681,31 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
     ]
     for (name, outs, sums, vfn, (xr, xc), (arr, dr, dc, slot), rd, guard, scale) in specs:
         isJ = arr == "J"
-        for o in outs:
+        # outputs in groups of g: the group's integrals stay in registers and
+        # each density's X block is gathered once per group, not per output
+        g = max(1, DIGEST_VALUES // len(sums))
+        for c0 in range(0, len(outs), g):
+            grp = outs[c0:c0 + g]
             out("{")
-            for t, sidx in enumerate(sums):
-                out(f"  const {T_()} w{t} = STL({vfn(o, sidx)});")
+            for u, o in enumerate(grp):
+                for t, sidx in enumerate(sums):
+                    out(f"  const {T_()} w{u}_{t} = STL({vfn(o, sidx)});")
             out("  for (int m = 0; m < dg.nX; ++m) {")
             out(f"    const int {slot} = dg.{'jslot' if isJ else 'kslot'}[m];")
             out(f"    if ({slot} < 0) continue;")
-            terms = " + ".join(f"w{t} * {cvx(f'ld_x(dg, mc, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)')}" for t, sidx in enumerate(sums))
-            sc = f"{lit(2)} * " if scale else ""
-            val = f"{sc}({terms})"
-            if rd == "red_all":
-                val = f"{red('red_i')}({red('red_j')}({val}))"
-            elif rd != "none":
-                val = f"{red(rd)}({val})"
+            for t, sidx in enumerate(sums):
+                out(f"    const {T_()} x{t} = {cvx(f'ld_x(dg, mc, {xr} + {sidx[0]}, {xc} + {sidx[1]}, m)')};")
             idxf = "jidx" if isJ else "kidx"
-            out(f"    const {T_()} s = {val};")
-            out(f"    if ({guard}) atomic_add(mc.{arr} + {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s);")
+            for u, o in enumerate(grp):
+                terms = " + ".join(f"w{u}_{t} * x{t}" for t in range(len(sums)))
+                sc = f"{lit(2)} * " if scale else ""
+                val = f"{sc}({terms})"
+                if rd == "red_all":
+                    val = f"{red('red_i')}({red('red_j')}({val}))"
+                elif rd != "none":
+                    val = f"{red(rd)}({val})"
+                out(f"    {{ const {T_()} s = {val};")
+                out(f"      if ({guard}) atomic_add(mc.{arr} + {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s); }}")
             out("  }")
             out("}")
 
