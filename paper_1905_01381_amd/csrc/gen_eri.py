@@ -650,7 +650,11 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
     return nodes
 
 
-DIGEST_VALUES = 36  # integrals a staged digestion group keeps in registers
+# Integrals a staged digestion group keeps in registers (measured per class:
+# larger groups share more density gathers until the kernel starts to
+# spill in the primitive loop).
+DIGEST_VALUES = 54
+DIGEST_VALUES_CLASS = {(2, 2, 2, 2): 72}
 
 
 def emit_staged_digest(out: Emitter, la, lb, lc, ld):
@@ -683,7 +687,7 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
         isJ = arr == "J"
         # outputs in groups of g: the group's integrals stay in registers and
         # each density's X block is gathered once per group, not per output
-        g = max(1, DIGEST_VALUES // len(sums))
+        g = max(1, DIGEST_VALUES_CLASS.get((la, lb, lc, ld), DIGEST_VALUES) // len(sums))
         for c0 in range(0, len(outs), g):
             grp = outs[c0:c0 + g]
             out("{")
