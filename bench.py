@@ -386,16 +386,25 @@ def main():
         gb.fock2e_2c(P2, out=G)
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
-    gb.profile(True, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
         gb.fock2e_2c(P2, out=G)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"[bench] {a.steps} timed steps done", file=sys.stderr, flush=True)
+    # roofline: the same steps again with per-class HIP events, which run the
+    # classes one after another so that each event pair times one kernel
+    gb.profile(True, reset=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(a.steps):
+        gb.fock2e_2c(P2, out=G)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     gb.profile(False)
     prof = gb.profile_read()
-    print(f"[bench] {a.steps} timed steps done", file=sys.stderr, flush=True)
+    print(f"[bench] {a.steps} per-class timed steps done", file=sys.stderr, flush=True)
     if a.calib_copy_mib > 0:
         nel = a.calib_copy_mib * (1 << 20) // 8
         x = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -451,6 +460,8 @@ def main():
             "flops_per_quartet": fq,
             "quartets_per_launch": counts[cls],
             "avg_launch_ms": avg_s * 1e3,
+            "timing": "per-class HIP events over a second timed pass of the same steps, classes serialized",
+            "serialized_ms_per_step": (t3 - t2) / a.steps * 1e3,
         },
         "per_class_ms": {"".join("spd"[x] for x in k): v[0] / v[1] for k, v in sorted(prof.items())},
     }

@@ -206,7 +206,10 @@ cq_status cq_autotune(cq_basis b, int nmat, int reps, hipStream_t stream);
 cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
 
 /* Per-class launch timing with HIP events recorded on the launch stream
- * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.
+ * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.  Builds
+ * normally run the classes concurrently on internal streams forked from the
+ * caller's stream; with timing on they run one after another on the
+ * caller's stream, so each time is one kernel's own.
  * cq_profile_read synchronizes on the recorded events and returns, per class
  * that ran, cls[4k..4k+3], the summed kernel time ms[k] and launch count
  * count[k]; *n = number of such classes. */

@@ -148,6 +148,24 @@ def test_sixteen_densities_mixed_symmetry(spd_case, torch_cuda):
         assert rel_err(K[m], Kr[m]) < TOL_JK, m
 
 
+def test_concurrent_classes_equal_serialized(spd_case, torch_cuda):
+    """Classes normally run concurrently on internal streams (the staged ones
+    in order on one of them, since they share the stage workspace); with
+    per-class timing on they run one after another.  Same J and K."""
+    torch = torch_cuda
+    w, ob, gb, P = spd_case
+    rng = np.random.default_rng(23)
+    mats = [P, inputs.random_symmetric(gb.nbf, rng, -1)]
+    J0, K0 = _jk_gpu(torch, gb, mats, [1, -1], want_j=[True, False])
+    gb.profile(True, reset=True)
+    J1, K1 = _jk_gpu(torch, gb, mats, [1, -1], want_j=[True, False])
+    gb.profile(False)
+    assert len(gb.profile_read()) > 0
+    assert rel_err(J1[0], J0[0]) < 1e-13
+    for m in range(2):
+        assert rel_err(K1[m], K0[m]) < 1e-13
+
+
 def test_tiles_span_rows_and_ragged_tail(torch_cuda):
     """12 atoms of 2s1p: rows of up to 5 tiles of 64 with ragged ends."""
     torch = torch_cuda
