@@ -414,8 +414,8 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
 # for a second wave per SIMD, which one wave alone cannot keep the FP64
 # pipeline busy without (measured per class on MI355X).
 STAGE_CFG = {
-    (2, 1, 1, 1): (24, 2),
-    (2, 1, 2, 1): (24, 2),
+    (2, 1, 1, 1): (40, 2),
+    (2, 1, 2, 1): (32, 2),
     (2, 2, 1, 1): (24, 2),
     (2, 2, 2, 0): (24, 2),
     (2, 2, 2, 1): (24, 2),
