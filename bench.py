@@ -365,8 +365,8 @@ def cpu_baseline(w, budget_s: float):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU design is described in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): the build shards by class tasks with one "
+              f"all-reduce of the J'/K' partial sums, which is not implemented here", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1905_01381_amd import cq, flops, inputs

@@ -5,8 +5,9 @@ Paper, "General Infrastructure for the Unified Treatment of Electronic Spin":
   2X^0 = X^aa + X^bb, 2X^1 = X^ab + X^ba, -2i X^2 = X^ab - X^ba,
   2X^3 = X^aa - X^bb.
 * Eq. 2c_expectation: Tr[O^{2C} P^{2C}] = 2 sum_I Tr[O^I P^I].
-Paper, "Reference Wave Functions", Eq. 2c_fock (read with the factor that the
-half in Eq. pauli_sep implies):
+Paper, "Reference Wave Functions", Eq. 2c_fock, read with the factor that
+the half in Eq. pauli_sep implies (with P^0 = (P^aa + P^bb)/2, the Coulomb
+term of the full density is 2 J[P^0]):
   G^0 = 2 J[P^0] - K[P^0],   G^k = -K[P^k]   (k = 1, 2, 3).
 
 The spin-blocked matrix is [[X^aa, X^ab], [X^ba, X^bb]] (rows/columns: all

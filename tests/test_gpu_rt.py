@@ -149,7 +149,7 @@ def test_mlp_kernels_against_oracle(torch_cuda):
 def test_learned_proposal_vs_plain(c1_state, torch_cuda):
     """Plain self-consistent midpoint vs the learned proposal: the network is
     trained on the first 150 steps of the run, then propagates 150 more steps;
-    an independent plain run is the judge.  The learned run needs fewer builds
+    an independent plain run is the reference.  The learned run needs fewer builds
     per step, its dipole stays within 1e-5 a.u. of the plain one, and the same
     run with the network zeroed (ablation: the proposal falls back to linear
     extrapolation) costs more builds."""
