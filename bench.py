@@ -61,6 +61,9 @@ def parse():
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l"])
+    ap.add_argument("--serialize", action="store_true",
+                    help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
+                         "kernel-trace profiler so that each kernel's duration is its own")
     ap.add_argument("--atoms", type=int, default=0, help="c3/c5: atoms (0 = the full workload)")
     ap.add_argument("--nmol", type=int, default=16, help="c4: number of molecules (smallest first)")
     ap.add_argument("--rt-steps", type=int, default=2000, help="c5l: trajectory length")
@@ -382,6 +385,8 @@ def main():
     counts = gb.quartet_counts()
     nq = sum(counts.values())
     print(f"[bench] nbf={gb.nbf} nshell={gb.nshell} unique shell quartets/build={nq:.4e}", file=sys.stderr, flush=True)
+    if a.serialize:
+        gb.profile(True, reset=True)
     for i in range(a.warmup):
         gb.fock2e_2c(P2, out=G)
         torch.cuda.synchronize()
