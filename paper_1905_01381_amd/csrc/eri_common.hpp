@@ -191,8 +191,9 @@ struct Digest {
     double skip;          // density-weighted Schwarz threshold (0: none)
     const double* pmax;   // block-diagonal [ns][ns] per molecule: max |X| per shell block
     int nshell;
-    int stage_blocks;     // waves that own a stage region (grid limit of staged classes)
-    double* stage;        // per-wave private stage, [stage_blocks][class stage size][64]
+    int pad_stage_;
+    double* stage;        // per-wave private stage, [wave][class stage size][64]
+    size_t stage_bytes;   // bytes of the stage workspace (caps the grid of staged classes)
     int mode;             // 0: FP64 everywhere; 1: precision-routed
     int acc_direct;       // 1: task-invariant partial sums go straight to J'/K' (no LDS room)
     double fp32_below;    // routed mode: a wave step whose largest bound is below this runs in FP32
