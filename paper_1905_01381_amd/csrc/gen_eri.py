@@ -411,14 +411,16 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
 
 # Per-class staging: (targets per pass, waves per SIMD the kernel is
 # compiled for).  Smaller passes re-run more of the VRR but free registers
-# for a second wave per SIMD, which one wave alone cannot keep the FP64
-# pipeline busy without (measured per class on MI355X).
+# for a second wave per SIMD; larger ones re-run less at one wave, which
+# leaves the FP64 pipeline partly idle.  Each class takes the measured
+# faster side on MI355X: (dd|pp) and (dd|dp) keep whole bra groups per pass
+# (7 and 3 bra components with every ket target) at one wave.
 STAGE_CFG = {
     (2, 1, 1, 1): (40, 2),
     (2, 1, 2, 1): (32, 2),
-    (2, 2, 1, 1): (24, 2),
+    (2, 2, 1, 1): (63, 1),
     (2, 2, 2, 0): (24, 2),
-    (2, 2, 2, 1): (24, 2),
+    (2, 2, 2, 1): (48, 1),
     (2, 2, 2, 2): (48, 1),
 }
 
