@@ -666,9 +666,10 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
 
 # Integrals a staged digestion group keeps in registers (measured per class:
 # larger groups share more density gathers until the kernel starts to
-# spill in the primitive loop).
+# spill in the primitive loop).  The one-wave classes have up to 512
+# registers per lane and take larger groups.
 DIGEST_VALUES = 54
-DIGEST_VALUES_CLASS = {(2, 2, 2, 2): 72}
+DIGEST_VALUES_CLASS = {(2, 2, 1, 1): 108, (2, 2, 2, 1): 108, (2, 2, 2, 2): 144}
 
 
 def emit_staged_digest(out: Emitter, la, lb, lc, ld):
