@@ -413,13 +413,14 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
 # compiled for).  Smaller passes re-run more of the VRR but free registers
 # for a second wave per SIMD; larger ones re-run less at one wave, which
 # leaves the FP64 pipeline partly idle.  Each class takes the measured
-# faster side on MI355X: (dd|pp) and (dd|dp) keep whole bra groups per pass
-# (7 and 3 bra components with every ket target) at one wave.
+# faster side on MI355X.  At one wave, (dd|pp) and (dd|dp) keep whole bra
+# groups per pass (7 and 3 bra components with every ket target) and (dd|ds)
+# runs four greedy passes.
 STAGE_CFG = {
     (2, 1, 1, 1): (40, 2),
     (2, 1, 2, 1): (32, 2),
     (2, 2, 1, 1): (63, 1),
-    (2, 2, 2, 0): (24, 2),
+    (2, 2, 2, 0): (48, 1),
     (2, 2, 2, 1): (48, 1),
     (2, 2, 2, 2): (48, 1),
 }
@@ -669,7 +670,7 @@ def emit_staged_eri(out: Emitter, la, lb, lc, ld):
 # spill in the primitive loop).  The one-wave classes have up to 512
 # registers per lane and take larger groups.
 DIGEST_VALUES = 54
-DIGEST_VALUES_CLASS = {(2, 2, 1, 1): 108, (2, 2, 2, 1): 108, (2, 2, 2, 2): 144}
+DIGEST_VALUES_CLASS = {(2, 2, 1, 1): 108, (2, 2, 2, 0): 108, (2, 2, 2, 1): 108, (2, 2, 2, 2): 144}
 
 
 def emit_staged_digest(out: Emitter, la, lb, lc, ld):
