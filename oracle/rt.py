@@ -6,6 +6,10 @@ the paper lists), and Fock matrices from the oracle's own J/K.
   F_FE-step: U_FE = exp(-i dt F'(P_k)), P_FE = U_FE P_k U_FE^dagger
   F'_m = (F'(P_k) + F'(P_FE)) / 2,  U = exp(-i dt F'_m),  P_{k+1} = U P_k U^dagger
 Closed shell, per-spin P: F = h + 2 J[Re P] - K[Re P] - i K[Im P].
+
+Also the self-consistent midpoint step (midpoint_step) and the paper's
+default leap-frog integrator, MMUT, with EM2 seed and restart steps
+(mmut_step, mmut_trajectory).
 """
 from __future__ import annotations
 
@@ -19,9 +23,8 @@ def expm_herm(H: np.ndarray, dt: float) -> np.ndarray:
 
 def fock_ortho(basis, h, X, Po):
     P = X @ Po @ X
-    J, Kr = basis.jk(P.real)
-    _, Ki = basis.jk(P.imag, want_j=False)
-    F = h + 2.0 * J - Kr - 1j * Ki
+    J, K = basis.jk(np.stack([P.real, P.imag]))
+    F = h + 2.0 * J[0] - K[0] - 1j * K[1]
     return X @ F @ X, P, F
 
 
@@ -39,3 +42,50 @@ def energy_dipole(basis, h, X, Dz, Po, enuc=0.0, mu_nuc=0.0):
     E = float(np.real(np.sum(P * np.conj(h + F)))) + enuc
     mu = -2.0 * float(np.real(np.sum(P * Dz))) + mu_nuc
     return E, mu
+
+
+def midpoint_step(basis, h, X, Po, dt, guess=None, tol=1e-12, max_iter=200):
+    """Self-consistent midpoint Magnus-2 step (the corrector the survey
+    names as the judge of the learned proposal): the midpoint density is
+    iterated to a fixed point,
+      P_mid^(i+1) = (P_k + U_i P_k U_i^dagger) / 2,  U_i = exp(-i dt F'(P_mid^(i))),
+    starting from `guess` (default P_k), until max|P_mid^(i+1) - P_mid^(i)|
+    < tol.  Returns (P_{k+1}, P_mid, iterations); P_{k+1} is the density the
+    last evaluated propagator gives."""
+    Pm = Po.copy() if guess is None else guess.copy()
+    for it in range(1, max_iter + 1):
+        F, _, _ = fock_ortho(basis, h, X, Pm)
+        U = expm_herm(F, dt)
+        Pn = U @ Po @ U.conj().T
+        Pm_new = 0.5 * (Po + Pn)
+        d = np.abs(Pm_new - Pm).max()
+        Pm = Pm_new
+        if d < tol:
+            return Pn, Pm, it
+    raise RuntimeError("midpoint iteration did not converge")
+
+
+def mmut_step(basis, h, X, P_prev, P_cur, dt):
+    """One leap-frog step of the modified midpoint unitary transformation
+    (paper: "Real-Time Electronic Dynamics", the MMUT propagator):
+    P_{k+1} = U P_{k-1} U^dagger with U = exp(-2 i dt F'(P_k))."""
+    F, _, _ = fock_ortho(basis, h, X, P_cur)
+    U = expm_herm(F, 2.0 * dt)
+    return U @ P_prev @ U.conj().T
+
+
+def mmut_trajectory(basis, h, X, P0, dt, nsteps, restart):
+    """MMUT with the paper's seed/restart step: step 0 -> 1 and every step
+    k with k % restart == 0 is an EM2 step from P_k alone; the others are
+    leap-frog steps.  Returns the list [P_0, ..., P_nsteps] and the Fock
+    builds each step used."""
+    Ps = [P0]
+    builds = []
+    for k in range(nsteps):
+        if k % restart == 0:
+            Ps.append(em2_step(basis, h, X, Ps[-1], dt))
+            builds.append(2)
+        else:
+            Ps.append(mmut_step(basis, h, X, Ps[-2], Ps[-1], dt))
+            builds.append(1)
+    return Ps, builds

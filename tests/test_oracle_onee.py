@@ -1,0 +1,116 @@
+"""Pins of the oracle's one-electron integrals (kinetic, nuclear attraction,
+dipole) against facts other than the oracle (no GPU).
+
+* Closed forms for one normalized primitive at the origin: <s|-lap/2|s> =
+  3a/2 and <p|-lap/2|p> = 5a/2; <s|1/r|s> = 2 sqrt(2a/pi) and
+  <p_z|1/r|p_z> = (4/3) sqrt(2a/pi) for a nucleus at the centre; <s_A|z|s_A>
+  = A_z.
+* Contracted matrices over s, p and d shells on two centres against
+  Gauss-Hermite quadrature (kinetic energy in its gradient form, dipole with
+  a shifted origin) and, for the nuclear attraction, against the
+  t-integral representation of 1/r with adaptive quadrature in t.
+The contraction coefficients and component factors come from the basis
+normalization, itself pinned by quadrature in test_oracle_pins.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_01381_amd import inputs
+from tests import quad
+
+
+def _one_prim(l, a, center):
+    return oracle.Basis(np.asarray(center, float).reshape(1, 3), [l], [1], [a], [1.0])
+
+
+@pytest.mark.parametrize("a", [0.13, 1.0, 7.5])
+def test_closed_forms_single_primitive(a):
+    s = _one_prim(0, a, (0.0, 0.0, 0.0))
+    assert s.one_electron("kinetic")[0, 0] == pytest.approx(1.5 * a, rel=1e-14)
+    V = s.one_electron("nuclear", charges=[2.0], centers=[[0.0, 0.0, 0.0]])[0, 0]
+    assert V == pytest.approx(-2.0 * 2.0 * np.sqrt(2 * a / np.pi), rel=1e-14)
+    p = _one_prim(1, a, (0.0, 0.0, 0.0))
+    T = p.one_electron("kinetic")
+    assert np.allclose(np.diag(T), 2.5 * a, rtol=1e-14, atol=0)
+    assert np.abs(T - np.diag(np.diag(T))).max() < 1e-15 * a
+    Vp = p.one_electron("nuclear", charges=[1.0], centers=[[0.0, 0.0, 0.0]])
+    assert np.allclose(np.diag(Vp), -(4.0 / 3.0) * np.sqrt(2 * a / np.pi), rtol=1e-14, atol=0)
+    A = np.array([0.3, -1.1, 2.7])
+    sA = _one_prim(0, a, A)
+    for d in range(3):
+        assert sA.one_electron("dipole", direction=d)[0, 0] == pytest.approx(A[d], rel=1e-14)
+        org = np.array([0.5, 0.25, -1.0])
+        got = sA.one_electron("dipole", direction=d, origin=org)[0, 0]
+        assert got == pytest.approx(A[d] - org[d], rel=1e-13)
+
+
+def _small():
+    rng = np.random.default_rng(12)
+    mol = inputs.make_molecule(2, [0, 1, 2], 0.3, 20.0, rng)
+    return mol, oracle.Basis.from_molecule(mol)
+
+
+def _functions(mol):
+    out = []
+    for s in range(mol.nshell):
+        for comp in quad.cart_components(int(mol.shell_l[s])):
+            out.append((s, comp))
+    return out
+
+
+def _contract(mol, B, prim, mu, nu):
+    coef, cnorm = B.normalized_coefs()
+    po = np.concatenate([[0], np.cumsum(mol.nprim)])
+    fs = _functions(mol)
+    (sa, ca), (sb, cb) = fs[mu], fs[nu]
+    tot = 0.0
+    for i in range(po[sa], po[sa + 1]):
+        for j in range(po[sb], po[sb + 1]):
+            tot += coef[i] * coef[j] * prim(ca, mol.alpha[i], mol.shell_xyz[sa], cb, mol.alpha[j], mol.shell_xyz[sb])
+    return tot * cnorm[mu] * cnorm[nu]
+
+
+def test_kinetic_matrix_by_quadrature():
+    mol, B = _small()
+    T = B.one_electron("kinetic")
+    n = B.nbf
+    ref = np.array([[_contract(mol, B, quad.kinetic_prim, m, v) for v in range(n)] for m in range(n)])
+    assert np.abs(T - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.allclose(T, T.T, atol=1e-14 * np.abs(T).max())
+    assert np.linalg.eigvalsh(T).min() > 0
+
+
+def test_dipole_matrix_by_quadrature():
+    mol, B = _small()
+    org = np.array([0.4, -0.7, 0.2])
+    n = B.nbf
+    for d in range(3):
+        D = B.one_electron("dipole", direction=d, origin=org)
+        prim = lambda ea, a, A, eb, b, Bc: quad.dipole_prim(ea, a, A, eb, b, Bc, org, d)
+        ref = np.array([[_contract(mol, B, prim, m, v) for v in range(n)] for m in range(n)])
+        assert np.abs(D - ref).max() < 1e-12 * np.abs(ref).max(), d
+
+
+def test_nuclear_matrix_by_quadrature():
+    """Sampled elements over every pair of angular momenta, three charges
+    (one on a basis centre, two off centre)."""
+    mol, B = _small()
+    Z = np.array([1.0, 2.5, 0.7])
+    C = np.array([mol.shell_xyz[0], [0.3, 0.9, -0.4], [-1.2, 0.1, 2.0]])
+    V = B.one_electron("nuclear", charges=Z, centers=C)
+    fs = _functions(mol)
+    by_l = {}
+    for mu, (s, _) in enumerate(fs):
+        by_l.setdefault(int(mol.shell_l[s]), []).append(mu)
+    rng = np.random.default_rng(3)
+    picks = [(by_l[la][rng.integers(len(by_l[la]))], by_l[lb][rng.integers(len(by_l[lb]))])
+             for la in (0, 1, 2) for lb in (0, 1, 2)]
+    scale = np.abs(V).max()
+    for mu, nu in picks:
+        ref = 0.0
+        for z, c in zip(Z, C):
+            prim = lambda ea, a, A, eb, b, Bc, c=c: quad.nuclear_prim(ea, a, A, eb, b, Bc, c)
+            ref -= z * _contract(mol, B, prim, mu, nu)
+        assert abs(V[mu, nu] - ref) < 1e-11 * scale, (mu, nu, V[mu, nu], ref)
+    assert np.allclose(V, V.T, atol=1e-14 * scale)
