@@ -26,11 +26,13 @@ Other workloads (one JSON line each, same top-level keys; not the headline):
                   time per step and per Fock build after an RHF ground state
                   and a delta kick; --atoms scales the molecule
   --workload c5l  the learned-midpoint protocol on the same recipe (default
-                  12 atoms): plain self-consistent midpoint for --rt-steps
-                  steps; the learned run records the first --rt-train steps,
-                  trains the network on the GPU, then proposes midpoints;
-                  the ablation zeroes the network.  Reports builds/step,
-                  dipole error vs plain and energy drift
+                  12 atoms): plain self-consistent midpoint, learned proposal
+                  (records the first --rt-train steps, trains the network on
+                  the GPU, then proposes midpoints) and its ablation (network
+                  zeroed), all at one first-iterate acceptance tolerance
+                  (--accept-tol); EM2 and MMUT beside them.  Reports
+                  builds/step, dipole error against a tightly converged
+                  midpoint trajectory and energy drift
 """
 from __future__ import annotations
 
@@ -69,6 +71,9 @@ def parse():
     ap.add_argument("--rt-steps", type=int, default=2000, help="c5l: trajectory length")
     ap.add_argument("--rt-train", type=int, default=500, help="c5l: steps recorded for training")
     ap.add_argument("--epochs", type=int, default=200, help="c5l: training epochs")
+    ap.add_argument("--accept-tol", type=float, default=1e-8,
+                    help="c5l: first-iterate acceptance tolerance shared by plain, learned and ablation")
+    ap.add_argument("--mmut-restart", type=int, default=50, help="c5l: MMUT EM2 restart period")
     return ap.parse_args()
 
 
@@ -184,7 +189,7 @@ def bench_c4(a, torch, cq, inputs):
         "speedup_batched_tuned_vs_per_molecule": t_single / t_tuned,
         "speedup_tuned_vs_default": t_default / t_tuned,
         "autotune_s": t_tune,
-        "plan": [{"cls": "".join("spd"[x] for x in p["cls"]), "cl": p["cl"], "grid": p["grid"],
+        "plan": [{"cls": "".join("spd"[x] for x in p["cls"]), "cl": p["cl"], "grid": p["grid"], "exchanged": p["exchanged"],
                   "ms": round(p["ms"], 3)} for p in plan],
     }
 
@@ -208,80 +213,103 @@ def _c5_state(a, torch, cq, inputs, natom):
     return gb, res, (d(res.h), d(X), d(Dz), d(P0))
 
 
-def _rt_steps(r, n, label, chunk=100):
-    """r.step(n) in chunks, with one progress line per chunk."""
-    Es, mus, nbs = [], [], []
+def _rt_steps(r, n, label, chunk=50):
+    """r.step(n) in chunks; the energy (one extra, uncounted Fock build) is
+    taken at the last step of each chunk only; one progress line per chunk.
+    Returns (steps with an energy, energies, dipoles, builds per step)."""
+    Es, Ei, mus, nbs = [], [], [], []
     done = 0
     while done < n:
         k = min(chunk, n - done)
-        E, mu, nb = r.step(k, energy=True)
-        Es.append(E)
+        if k > 1:
+            _, mu, nb = r.step(k - 1, energy=False)
+            mus.append(mu)
+            nbs.append(nb)
+        E, mu, nb = r.step(1, energy=True)
         mus.append(mu)
         nbs.append(nb)
         done += k
+        Es.append(float(E[0]))
+        Ei.append(done - 1)
         _log(f"{label}: {done}/{n} steps, {np.concatenate(nbs).mean():.3f} builds/step")
-    return np.concatenate(Es), np.concatenate(mus), np.concatenate(nbs)
+    return np.array(Ei), np.array(Es), np.concatenate(mus), np.concatenate(nbs)
 
 
 def bench_c5l(a, torch, cq, inputs):
-    """Learned midpoint proposal vs the plain self-consistent midpoint
-    corrector on the C5 recipe (reduced molecule), same initial state."""
+    """Builds per step of the learned midpoint proposal against the plain
+    self-consistent midpoint corrector and its own ablation (network zeroed:
+    the propagator-reuse baseline alone), all accepting the first midpoint
+    iterate at the same tolerance; EM2 (2 builds/step) and MMUT (1 build per
+    step plus EM2 restarts) beside them.  Dipole errors are measured against
+    a reference midpoint trajectory converged to 1e-12."""
     natom = a.atoms or 12
     gb, res, args = _c5_state(a, torch, cq, inputs, natom)
-    dt, nt, nall = 0.05, a.rt_train, a.rt_steps
-    t0 = time.perf_counter()
-    plain = cq.RT(gb, *args, dt, cq.RT_MIDPOINT)
-    plain.set_params(sc_tol=1e-10, max_iter=40)
-    E_p, mu_p, nb_p = _rt_steps(plain, nall, "plain midpoint")
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    _log(f"plain midpoint: {nall} steps, {nb_p.mean():.3f} builds/step, {t_plain:.1f} s")
+    dt, nt, nall, acc = 0.05, a.rt_train, a.rt_steps, a.accept_tol
+    runs = {}
 
-    def learned(epochs, zero):
+    def plain(mode, label, sc_tol=1e-10, accept=acc, restart=None):
+        r = cq.RT(gb, *args, dt, mode)
+        r.set_params(sc_tol=sc_tol, max_iter=60, accept_tol=accept)
+        if restart:
+            r.set_restart(restart)
+        t0 = time.perf_counter()
+        ei, E, mu, nb = _rt_steps(r, nall, label)
+        torch.cuda.synchronize()
+        runs[label] = {"E_idx": ei, "E": E, "mu": mu, "nb": nb, "s": time.perf_counter() - t0, "stats": r.stats()}
+        r.close()
+
+    def learned(zero, label):
         r = cq.RT(gb, *args, dt, cq.RT_MIDPOINT)
-        r.set_params(sc_tol=1e-10, max_iter=40, accept_tol=1e-6)
+        r.set_params(sc_tol=1e-10, max_iter=60, accept_tol=acc)
         r.record(True, 4096, 1)
         t0 = time.perf_counter()
-        E1, mu1, nb1 = _rt_steps(r, nt, "recording")
+        e1, E1, mu1, nb1 = _rt_steps(r, nt, label + " (recording)")
         r.record(False)
         t1 = time.perf_counter()
-        loss = r.train(epochs=epochs, lr=3e-3)
+        loss = r.train(epochs=0 if zero else a.epochs, lr=3e-3)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t1
         if zero:
             r.weights(np.zeros(354, np.float32))
         r.set_mode(cq.RT_LEARNED)
         t2 = time.perf_counter()
-        E2, mu2, nb2 = _rt_steps(r, nall - nt, "ablation" if zero else "learned")
+        e2, E2, mu2, nb2 = _rt_steps(r, nall - nt, label)
         torch.cuda.synchronize()
-        t_run = time.perf_counter() - t2
-        st = r.stats()
+        runs[label] = {"E_idx": np.concatenate([e1, e2 + nt]), "E": np.concatenate([E1, E2]),
+                       "mu": np.concatenate([mu1, mu2]), "nb": np.concatenate([nb1, nb2]),
+                       "s": time.perf_counter() - t2, "s_record": t1 - t0, "s_train": t_train, "loss": loss,
+                       "stats": r.stats()}
         r.close()
-        return (np.concatenate([E1, E2]), np.concatenate([mu1, mu2]), np.concatenate([nb1, nb2]), loss, t_train,
-                t_run, st, t1 - t0)
 
-    E_l, mu_l, nb_l, loss, t_train, t_run, st, t_rec = learned(a.epochs, False)
-    _log(f"learned: loss {loss:.3e}, train {t_train:.2f} s, {nb_l[nt:].mean():.3f} builds/step after training")
-    E_z, mu_z, nb_z, _, _, t_run_z, st_z, _ = learned(0, True)
-    _log(f"ablation: {nb_z[nt:].mean():.3f} builds/step")
-    err = float(np.abs(mu_l - mu_p).max())
-    err_z = float(np.abs(mu_z - mu_p).max())
-    per_step_plain = t_plain / nall
+    plain(cq.RT_MIDPOINT, "reference", sc_tol=1e-12, accept=1e-12)
+    plain(cq.RT_MIDPOINT, "plain")
+    learned(False, "learned")
+    learned(True, "ablation")
+    plain(cq.RT_EM2, "em2")
+    plain(cq.RT_MMUT, "mmut", restart=a.mmut_restart)
+    mu_ref = runs["reference"]["mu"]
+    out = {}
+    for k, r in runs.items():
+        after = r["nb"][nt:]
+        out[k] = {"builds_per_step": float(after.mean()),
+                  "max_dipole_err_vs_reference": float(np.abs(r["mu"] - mu_ref).max()),
+                  "energy_drift": float(np.abs(r["E"] - r["E"][0]).max()),
+                  "s_per_step": r["s"] / (nall - nt if k in ("learned", "ablation") else nall),
+                  "stats": r["stats"]}
+    for k in ("learned", "ablation"):
+        out[k]["train_loss"] = runs[k]["loss"]
+        out[k]["train_s"] = runs[k]["s_train"]
     return {
-        "metric": "RT-TDSCF J/K builds per step: learned midpoint proposal vs plain self-consistent midpoint",
-        "value": float(nb_l[nt:].mean()), "unit": "builds/step", "n_gpus": 1, "steps": nall - nt, "warmup": nt,
-        "ms_per_step": t_run / (nall - nt) * 1e3, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64 (MLP f32)", "data": "synthetic",
+        "metric": "RT-TDSCF J/K builds per step: learned midpoint proposal vs plain midpoint corrector at equal "
+                  "acceptance tolerance",
+        "value": out["learned"]["builds_per_step"], "unit": "builds/step", "n_gpus": 1, "steps": nall - nt,
+        "warmup": nt, "ms_per_step": out["learned"]["s_per_step"] * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (MLP f32)", "data": "synthetic",
         "config": {"workload": f"RT-TDSCF learned midpoint: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, "
-                               f"{natom // 2} doubly occupied; kick 1e-4 along z; dt 0.05; {nall} steps, "
-                               f"network trained on the first {nt}", "nbf": gb.nbf},
-        "plain_builds_per_step": float(nb_p[nt:].mean()),
-        "ablation_builds_per_step": float(nb_z[nt:].mean()),
-        "max_dipole_diff_learned_vs_plain": err, "max_dipole_diff_ablation_vs_plain": err_z,
-        "energy_drift_plain": float(np.abs(E_p - E_p[0]).max()),
-        "energy_drift_learned": float(np.abs(E_l - E_l[0]).max()),
-        "ms_per_step_plain": per_step_plain * 1e3, "ms_per_step_ablation": t_run_z / (nall - nt) * 1e3,
-        "train_loss": loss, "train_s": t_train, "record_s": t_rec, "stats_learned": st, "stats_ablation": st_z,
+                               f"{natom // 2} doubly occupied; kick 1e-4 along z; dt 0.05; {nall} steps, network "
+                               f"trained on the first {nt}; first-iterate acceptance {acc:g} for plain, learned "
+                               f"and ablation; MMUT restart every {a.mmut_restart} steps", "nbf": gb.nbf},
+        "runs": out,
     }
 
 
@@ -382,19 +410,20 @@ def main():
         return
     w, gb, P2 = build_inputs(torch, cq, inputs)
     G = torch.empty_like(P2)
+    th = cq.thresholds()
     counts = gb.quartet_counts()
     nq = sum(counts.values())
     print(f"[bench] nbf={gb.nbf} nshell={gb.nshell} unique shell quartets/build={nq:.4e}", file=sys.stderr, flush=True)
     if a.serialize:
         gb.profile(True, reset=True)
     for i in range(a.warmup):
-        gb.fock2e_2c(P2, out=G)
+        gb.fock2e_2c(P2, th=th, out=G)
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        gb.fock2e_2c(P2, out=G)
+        gb.fock2e_2c(P2, th=th, out=G)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"[bench] {a.steps} timed steps done", file=sys.stderr, flush=True)
@@ -404,7 +433,7 @@ def main():
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for i in range(a.steps):
-        gb.fock2e_2c(P2, out=G)
+        gb.fock2e_2c(P2, th=th, out=G)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     gb.profile(False)
@@ -452,6 +481,7 @@ def main():
             "nbf": gb.nbf,
             "quartets_per_build": nq,
             "mode": "fp64",
+            "accumulation": "deterministic fixed point",
         },
         "quartets_per_s": nq * builds_s,
         "roofline": {

@@ -49,7 +49,7 @@ typedef enum {
 
 typedef struct cq_basis_s* cq_basis;
 
-/* Thresholds of one build.
+/* Thresholds of one build (NULL = exact FP64, deterministic, overwrite).
  *   skip:       quartets whose bound Q_ab Q_cd max|X| (Schwarz factors times
  *               the largest density element of the six shell blocks the
  *               quartet touches, maximized over all densities; the paper's
@@ -62,7 +62,13 @@ typedef struct cq_basis_s* cq_basis;
  *               sums folded into the FP64 J and K; the Boys function for
  *               T >= 36 or order >= 6 stays FP64.  Other batches run in FP64.
  *   mode:       0 = FP64 throughout; 1 = precision-routed.
- *   flags:      CQ_ACCUMULATE adds into J/K instead of overwriting them. */
+ *   flags:      CQ_ACCUMULATE adds into J/K instead of overwriting them.
+ *               CQ_DETERMINISTIC (accepted, always in effect): partial sums
+ *               are accumulated as exact fixed-point integers (a scale 2^S
+ *               chosen per build from a bound of the sums, two 64-bit words
+ *               per element), so two builds of the same inputs give bitwise
+ *               equal J and K whatever the order of the device's additions.
+ *               Other bits: CQ_EINVAL. */
 typedef struct {
     double skip;
     double fp32_below;
@@ -71,6 +77,7 @@ typedef struct {
 } cq_thresholds;
 
 #define CQ_ACCUMULATE 1u
+#define CQ_DETERMINISTIC 2u
 #define CQ_MAX_DENSITIES 16
 
 /* Thread-local message describing the last failure ("" if none). */
@@ -131,15 +138,37 @@ int cq_basis_nshell(cq_basis b);
  * the DEVICE buffer Q (stream-ordered). */
 cq_status cq_schwarz(cq_basis b, double* Q, hipStream_t stream);
 
+/* Size limit of the build kernels, which address a molecule's interleaved
+ * [nbf][nbf][slots] blocks with 32-bit element offsets: returns CQ_OK if
+ * nbf^2 * max(nx, nj, nk) < 2^31, else CQ_EUNSUPPORTED (CQ_EINVAL for
+ * negative arguments).  nbf is the largest molecule's function count; nx, nj,
+ * nk are the density, Coulomb and exchange slots of one integral pass
+ * (cq_jk_build: nmat and the non-NULL J / K entries; cq_fock2e_2c: 8, 1, 8).
+ * Host only.  cq_jk_build, cq_fock2e_2c and cq_autotune apply it to their own
+ * arguments before any work is enqueued. */
+cq_status cq_jk_size_check(int nbf, int nx, int nj, int nk);
+
+/* Device status of a basis: synchronizes `stream`, then returns
+ * CQ_ENONFINITE if a density packed by a build on this basis since the last
+ * call held a NaN or infinity (the packing kernels set a device status word;
+ * J and K of such a build are not meaningful), CQ_OK otherwise.  Reading
+ * clears the word. */
+cq_status cq_sync_status(cq_basis b, hipStream_t stream);
+
 /* Coulomb and exchange matrices of nmat densities in one integral pass.
- *   nmat        1..CQ_MAX_DENSITIES
+ *   nmat        1..CQ_MAX_DENSITIES internal slots (see sym)
  *   P[nmat]     host array of device pointers to the densities X_m
  *               (nbf x nbf row-major; for a batch handle, the concatenated
  *               per-molecule blocks described at cq_basis_create_batch)
  *   sym[nmat]   +1 if X_m is symmetric, -1 if antisymmetric (only that part
  *               of X_m is used; e.g. the imaginary part of a Hermitian
  *               density is antisymmetric, paper: the remark on the
- *               symmetry of X^I after Eq. spin_generalization)
+ *               symmetry of X^I after Eq. spin_generalization), 0 for a
+ *               general real matrix with no symmetry, such as the transition
+ *               densities of the direct response sigma-vectors (paper:
+ *               "Residue Methods"); it is split into its symmetric and
+ *               antisymmetric parts, takes two of the CQ_MAX_DENSITIES
+ *               internal slots, and J[X] = J[X_s], K[X] = K[X_s] + K[X_a]
  *   J[nmat]     host array of device output pointers; an entry may be NULL
  *               (no Coulomb matrix wanted); must be NULL where sym = -1
  *               (J of an antisymmetric density vanishes).  J itself may be
@@ -190,19 +219,23 @@ cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, in
 cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t stream);
 
 /* Autotuner for the electron-repulsion launches of this handle: for every
- * class it times candidate task shapes (length of the c range one wave
- * walks: the default, half, twice and four times it) and grid caps (one wave
- * per task, or 2048 waves looping over tasks) with HIP events, each `reps`
- * times (1..100), on a synthetic density of nmat slots, and keeps the
- * fastest for every later build on the handle.  Results do not depend on the
+ * class it times candidate orientations (as generated, and with bra and ket
+ * exchanged where that kernel exists), task shapes (length of the c range
+ * one wave walks: the default, half, twice and four times it, at most 64) and
+ * grid caps (one wave per task, or 2048 waves looping over tasks) with HIP
+ * events, each `reps` times (1..100), on a synthetic density of nmat slots,
+ * and keeps the fastest for every later build on the handle.  Results do not depend on the
  * choice beyond the order of floating-point atomic additions.  Synchronizes
  * `stream`; overwrites the handle's work buffers only. */
 cq_status cq_autotune(cq_basis b, int nmat, int reps, hipStream_t stream);
 
 /* The launch plan per class (tuned or default): for k < cap,
- * rec[7k..7k+6] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks) and
- * ms[k] = best time measured by cq_autotune (0 if not tuned); *n = classes
- * with work.  Host arrays. */
+ * rec[8k..8k+7] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks,
+ * exchanged) and ms[k] = best time measured by cq_autotune (0 if not tuned);
+ * *n = classes with work.  exchanged = 1: the class runs with bra and ket
+ * pairs exchanged, (lc ld|la lb), which loops over the other pair's first
+ * shell and flushes fewer exchange partial sums per step (built for (pp|ps),
+ * (dp|ps), (dp|ds) and (dd|ps); the default there).  Host arrays. */
 cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
 
 /* Per-class launch timing with HIP events recorded on the launch stream
@@ -223,6 +256,7 @@ typedef struct cq_rt_s* cq_rt;
 #define CQ_RT_EM2 0       /* explicit 2nd-order Magnus (the paper's EM2), 2 builds/step */
 #define CQ_RT_MIDPOINT 1  /* self-consistent midpoint Magnus-2 corrector */
 #define CQ_RT_LEARNED 2   /* MLP midpoint proposal, corrector as fallback */
+#define CQ_RT_MMUT 3      /* the paper's leap-frog MMUT, EM2 seed / restart, 1 build/step */
 
 /* Propagator for a closed-shell density (P per spin, total 2P) in the
  * Loewdin orthonormal basis.  All matrix arguments are DEVICE buffers,
@@ -241,9 +275,18 @@ cq_status cq_rt_create(cq_basis b, const double* h, const double* X, const doubl
 cq_status cq_rt_destroy(cq_rt rt);
 cq_status cq_rt_set_mode(cq_rt rt, int mode);
 /* Midpoint convergence: max |P_mid^(i+1) - P_mid^(i)| < sc_tol within
- * max_iter builds (else CQ_ENOTCONV); learned proposals are accepted when
- * max |(P_k + P_{k+1})/2 - P_mid^pred| < accept_tol. */
+ * max_iter builds (else CQ_ENOTCONV).  The first iterate of a midpoint or
+ * learned step (the extrapolated guess, or the learned proposal) is accepted
+ * when max |(P_k + P_{k+1})/2 - P_mid^(0)| < accept_tol (default 1e-10 =
+ * the default sc_tol); both modes use the same acceptance, so their builds
+ * per step compare at one tolerance. */
 cq_status cq_rt_set_params(cq_rt rt, double sc_tol, int max_iter, double accept_tol);
+/* MMUT (paper: "Real-Time Electronic Dynamics", the MMUT equation and the
+ * EM2 seed / restart paragraph): P_{k+1} = U P_{k-1} U^dagger with
+ * U = exp(-2 i dt F'(P_k)).  Step n of the handle (counted from creation) is
+ * an EM2 step from P_k when n % period == 0 or no P_{k-1} exists yet, a
+ * leap-frog step otherwise.  period >= 1 (default 1000). */
+cq_status cq_rt_set_restart(cq_rt rt, int period);
 /* Advance nsteps steps; per step (HOST arrays, each may be NULL): the
  * electronic energy Re Tr[P(h + F)] (costs one extra, uncounted build),
  * the electronic dipole -2 Re Tr[D_z P] (Eq. td_expectation), and the
@@ -274,15 +317,24 @@ cq_status cq_rt_mlp_scales(cq_rt rt, float* feature_scale8, double* out_scale);
  * samples X [ns][8], targets Y [ns][2]; one Adam step (beta 0.9/0.999,
  * eps 1e-8) on DEVICE w, g, m, v (354 each). */
 cq_status cq_expm(int n, const double* H, double dt, double* U, hipStream_t stream);
+/* C = A op(B) for DEVICE row-major complex n x n matrices (interleaved re,
+ * im), op(B) = B (conjB = 0) or B^H (conjB = 1): the complex GEMM of every
+ * real-time product, on the FP64 matrix cores.  C must not alias A or B
+ * (CQ_EINVAL).  Asynchronous on `stream`. */
+cq_status cq_zgemm(int n, const double* A, const double* B, int conjB, double* C, hipStream_t stream);
 cq_status cq_mlp_eval(const float* w354, const float* X, const float* Y, int ns, float* grad, float* loss,
                       hipStream_t stream);
 cq_status cq_mlp_adam(float* w, const float* g, float* m, float* v, float lr, int step, hipStream_t stream);
 
 /* ---- test-only exports ------------------------------------------------ */
 
-/* Boys function F_m(T) for m = 0..mmax (mmax <= 16) at n points, FP64.
- * T: device [n]; F: device [n][mmax+1].  Asynchronous on `stream`. */
-cq_status cq_boys(int mmax, int n, const double* T, double* F, hipStream_t stream);
+/* Boys function F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt for m = 0..mmax
+ * (mmax <= 16) at n points.  T: device [n]; F: device [n][mmax+1] (FP64).
+ * fp32 = 0: the FP64 evaluation of the FP64 kernels; fp32 = 1: the one of
+ * the precision-routed FP32 kernels (T rounded to FP32; FP32 Chebyshev table
+ * and recursion for mmax < 6 and T < 36, FP64 rounded to FP32 otherwise),
+ * widened to FP64.  Asynchronous on `stream`. */
+cq_status cq_boys(int mmax, int n, const double* T, double* F, int fp32, hipStream_t stream);
 
 /* One contracted, normalized shell-quartet block (ab|cd), layout
  * [na][nb][nc][nd], written to HOST memory `out` (synchronizes `stream`). */

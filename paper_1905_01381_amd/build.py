@@ -83,7 +83,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
             objs.append(obj)
             logs.append(log)
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocblas"]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     if verbose:

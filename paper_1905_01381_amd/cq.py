@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcq.so")
 
 CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EHIP, CQ_EUNSUPPORTED, CQ_ENONFINITE, CQ_ENOTCONV = range(7)
 CQ_ACCUMULATE = 1
+CQ_DETERMINISTIC = 2
 CQ_MAX_DENSITIES = 16
 _STATUS = {0: "CQ_OK", 1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EHIP", 4: "CQ_EUNSUPPORTED",
            5: "CQ_ENONFINITE", 6: "CQ_ENOTCONV"}
@@ -60,7 +61,9 @@ def lib():
         L.cq_jk_build.argtypes = [vp, i, ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(Thresholds), vp]
         L.cq_fock2e_2c.argtypes = [vp, vp, vp, ctypes.POINTER(Thresholds), vp]
-        L.cq_boys.argtypes = [i, i, vp, vp, vp]
+        L.cq_boys.argtypes = [i, i, vp, vp, i, vp]
+        L.cq_sync_status.argtypes = [vp, vp]
+        L.cq_jk_size_check.argtypes = [i, i, i, i]
         L.cq_eri_quartet.argtypes = [vp, i, i, i, i, dp, vp]
         L.cq_one_electron.argtypes = [vp, i, i, dp, i, dp, dp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
@@ -72,6 +75,7 @@ def lib():
         L.cq_rt_destroy.argtypes = [vp]
         L.cq_rt_set_mode.argtypes = [vp, i]
         L.cq_rt_set_params.argtypes = [vp, ctypes.c_double, i, ctypes.c_double]
+        L.cq_rt_set_restart.argtypes = [vp, i]
         L.cq_rt_step.argtypes = [vp, i, dp, dp, ip]
         L.cq_rt_density.argtypes = [vp, vp, vp]
         L.cq_rt_stats.argtypes = [vp, llp]
@@ -81,6 +85,7 @@ def lib():
         L.cq_rt_mlp_weights.argtypes = [vp, fp, fp]
         L.cq_rt_mlp_scales.argtypes = [vp, fp, dp]
         L.cq_expm.argtypes = [i, vp, ctypes.c_double, vp, vp]
+        L.cq_zgemm.argtypes = [i, vp, vp, i, vp, vp]
         L.cq_mlp_eval.argtypes = [vp, vp, vp, i, vp, vp, vp]
         L.cq_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, i, vp]
         L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
@@ -90,7 +95,7 @@ def lib():
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
                      "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
-                     "cq_mlp_eval", "cq_mlp_adam"):
+                     "cq_mlp_eval", "cq_mlp_adam", "cq_sync_status", "cq_jk_size_check", "cq_rt_set_restart", "cq_zgemm"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -130,7 +135,14 @@ class JKResult:
 
 
 def thresholds(skip: float = 0.0, fp32_below: float = 0.0, mode: int = 0, accumulate: bool = False) -> Thresholds:
-    return Thresholds(float(skip), float(fp32_below), int(mode), CQ_ACCUMULATE if accumulate else 0)
+    """Build thresholds (accumulation is always deterministic: CQ_DETERMINISTIC)."""
+    flags = (CQ_ACCUMULATE if accumulate else 0) | CQ_DETERMINISTIC
+    return Thresholds(float(skip), float(fp32_below), int(mode), flags)
+
+
+def jk_size_check(nbf: int, nx: int, nj: int, nk: int) -> int:
+    """Status of cq_jk_size_check (host only): CQ_OK or CQ_EUNSUPPORTED."""
+    return int(lib().cq_jk_size_check(int(nbf), int(nx), int(nj), int(nk)))
 
 
 class Basis:
@@ -202,15 +214,15 @@ class Basis:
     def plan(self) -> list:
         """The launch plan per class: (la, lb, lc, ld), c-range length, grid cap, tasks, tuned ms."""
         n = ctypes.c_int()
-        rec = np.zeros(7 * 32, np.int32)
+        rec = np.zeros(8 * 32, np.int32)
         ms = np.zeros(32, np.float32)
         _check(lib().cq_autotune_read(self.h, 32, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                       ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
         out = []
         for k in range(min(n.value, 32)):
-            r = rec[7 * k:7 * k + 7]
+            r = rec[8 * k:8 * k + 8]
             out.append({"cls": tuple(int(x) for x in r[:4]), "cl": int(r[4]), "grid": int(r[5]),
-                        "tasks": int(r[6]), "ms": float(ms[k])})
+                        "tasks": int(r[6]), "exchanged": int(r[7]), "ms": float(ms[k])})
         return out
 
     def close(self):
@@ -293,6 +305,11 @@ class Basis:
         _check(lib().cq_quartet_counts(self.h, 64, cls, cnt, ctypes.byref(n)))
         return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
 
+    def sync_status(self, stream=None) -> int:
+        """cq_sync_status: CQ_OK, or CQ_ENONFINITE if a density of a build since
+        the last call held a non-finite element (the word is cleared)."""
+        return int(lib().cq_sync_status(self.h, _stream(stream)))
+
     def build_stats(self, stream=None) -> dict:
         """Quartets of the last build: evaluated in FP64 / FP32, skipped."""
         out = (ctypes.c_ulonglong * 3)()
@@ -319,16 +336,17 @@ class Basis:
         return out
 
 
-def boys(mmax: int, T, stream=None):
-    """F_m(T), m = 0..mmax, for a device float64 vector T -> [n, mmax+1]."""
+def boys(mmax: int, T, fp32: bool = False, stream=None):
+    """F_m(T), m = 0..mmax, for a device float64 vector T -> [n, mmax+1]
+    (fp32: the evaluation of the precision-routed FP32 kernels)."""
     import torch
     _req_dev(T, torch.float64)
     F = torch.empty((T.numel(), mmax + 1), dtype=torch.float64, device=T.device)
-    _check(lib().cq_boys(int(mmax), int(T.numel()), _ptr(T), _ptr(F), _stream(stream)))
+    _check(lib().cq_boys(int(mmax), int(T.numel()), _ptr(T), _ptr(F), int(bool(fp32)), _stream(stream)))
     return F
 
 
-RT_EM2, RT_MIDPOINT, RT_LEARNED = 0, 1, 2
+RT_EM2, RT_MIDPOINT, RT_LEARNED, RT_MMUT = 0, 1, 2, 3
 MLP_PARAMS = 354
 
 
@@ -363,8 +381,14 @@ class RT:
     def set_mode(self, mode: int):
         _check(lib().cq_rt_set_mode(self.h, int(mode)))
 
-    def set_params(self, sc_tol=1e-10, max_iter=30, accept_tol=1e-8):
-        _check(lib().cq_rt_set_params(self.h, float(sc_tol), int(max_iter), float(accept_tol)))
+    def set_params(self, sc_tol=1e-10, max_iter=30, accept_tol=None):
+        """accept_tol: first-iterate acceptance (default: sc_tol)."""
+        acc = sc_tol if accept_tol is None else accept_tol
+        _check(lib().cq_rt_set_params(self.h, float(sc_tol), int(max_iter), float(acc)))
+
+    def set_restart(self, period: int):
+        """MMUT: EM2 seed/restart every `period` steps."""
+        _check(lib().cq_rt_set_restart(self.h, int(period)))
 
     def step(self, nsteps: int, energy: bool = False, dipole: bool = True):
         E = np.zeros(nsteps)
@@ -423,6 +447,16 @@ def expm(H, dt: float, stream=None):
     U = torch.empty_like(H)
     _check(lib().cq_expm(int(H.shape[0]), _ptr(H), float(dt), _ptr(U), _stream(stream)))
     return U
+
+
+def zgemm(A, B, conj_b: bool = False, stream=None):
+    """A @ B (or A @ B^H) for device complex128 square matrices (cq_zgemm)."""
+    import torch
+    _req_dev(A, torch.complex128)
+    _req_dev(B, torch.complex128, tuple(A.shape))
+    C = torch.empty_like(A)
+    _check(lib().cq_zgemm(int(A.shape[0]), _ptr(A), _ptr(B), int(bool(conj_b)), _ptr(C), _stream(stream)))
+    return C
 
 
 def mlp_eval(w, X, Y, stream=None):

@@ -161,6 +161,13 @@ struct TaskMap {
     const int* shl_d;
     const MolInfo* mols;
     int ntask, pad_;
+    // screened or routed builds: the tasks of one precision (list[0 ..
+    // *list_n)) and per task the steps of each precision (masks[2 t] FP64,
+    // masks[2 t + 1] FP32; bit k = step c_lo + k).  list = NULL: every task,
+    // every step (c ranges are at most 64 steps).
+    const int* list;
+    const int* list_n;
+    const unsigned long long* masks;
 };
 
 // Sums over the 8 lanes sharing i (lanes 8i..8i+7) / sharing j.
@@ -183,7 +190,7 @@ __device__ __forceinline__ double red_i(double v)
 // molecule's block.
 struct Digest {
     const double* X;  // per molecule [nbf][nbf][nX], scaled by component factors
-    double* J;        // per molecule [nbf][nbf][nJ] partial sums J'
+    double* J;        // per molecule [nbf][nbf][nJ] partial sums J' (two fixed-point words each)
     double* K;        // per molecule [nbf][nbf][nK] partial sums K'
     int nbf, nX, nJ, nK;
     int jslot[CQ_MAX_MAT];
@@ -195,9 +202,14 @@ struct Digest {
     double* stage;        // per-wave private stage, [wave][class stage size][64]
     size_t stage_bytes;   // bytes of the stage workspace (caps the grid of staged classes)
     int mode;             // 0: FP64 everywhere; 1: precision-routed
-    int acc_direct;       // 1: task-invariant partial sums go straight to J'/K' (no LDS room)
+    int acc_lvl;          // task-invariant partial sums kept in LDS over a task: 0 none (straight to
+                          // J'/K'), 1 J'_ab and K'_ad, 2 also K'_bd (unstaged classes)
     double fp32_below;    // routed mode: a wave step whose largest bound is below this runs in FP32
     unsigned long long* counts;  // [3]: quartets evaluated in FP64, in FP32, skipped by screening
+    // J' and K' hold each element as two 64-bit integers, the fixed-point
+    // limbs of fx_add, side by side; fx[0] = 2^S is the build's fixed-point
+    // scale (computed on the device from the inputs), fx[1] = 2^-S.
+    const double* fx;
 };
 
 // One molecule's blocks as seen by a task: uniform base pointers plus
@@ -210,6 +222,7 @@ struct MolView {
     const int* ppos;
     const double* pmax;
     int nbf, s0, ns;
+    double fxs;  // fixed-point scale 2^S
 };
 
 __device__ __forceinline__ MolView mol_view(const Digest& dg, const TaskMap& tm, int m)
@@ -217,13 +230,14 @@ __device__ __forceinline__ MolView mol_view(const Digest& dg, const TaskMap& tm,
     const MolInfo mi = tm.mols[m];
     MolView v;
     v.X = dg.X + mi.xoff * dg.nX;
-    v.J = dg.J + mi.xoff * dg.nJ;
-    v.K = dg.K + mi.xoff * dg.nK;
+    v.J = dg.J + 2 * mi.xoff * dg.nJ;
+    v.K = dg.K + 2 * mi.xoff * dg.nK;
     v.ppos = tm.ppos + mi.soff;
     v.pmax = dg.pmax + mi.soff;
     v.nbf = mi.nbf;
     v.s0 = mi.s0;
     v.ns = mi.ns;
+    v.fxs = dg.fx[0];
     return v;
 }
 __device__ __forceinline__ double ld_x(const Digest& dg, const MolView& mc, int mu, int nu, int m)
@@ -242,9 +256,46 @@ __device__ __forceinline__ int kidx(const Digest& dg, const MolView& mc, int mu,
 // molecule's [ns][ns] tables
 __device__ __forceinline__ int spair(const MolView& mc, int a, int b) { return (a - mc.s0) * mc.ns + (b - mc.s0); }
 
-__device__ __forceinline__ void atomic_add(double* p, double v)
+// Accumulation by exact fixed-point integers, so that results do not depend
+// on the order in which waves add (the technique of reproducible GPU force
+// summation, e.g. Le Grand, Goetz and Walker's SPFP, Comput. Phys. Commun.
+// 184, 374 (2013), taken to two limbs): a contribution x becomes the integer
+// w = rint(x 2^S), |w| < 2^91, split as w = hi 2^31 + lo with
+// 0 <= lo < 2^31.  hi adds into the element's first 64-bit word and lo into
+// the second, with no carries between them; integer addition is associative,
+// so every sum is the same whatever the order.  The low word takes up to
+// 2^32 contributions per element.
+__device__ __forceinline__ void fx_add(double* p, double x, double scale)
 {
-    unsafeAtomicAdd(p, v);
+    const double w = rint(x * scale);
+    const double t = floor(w * 0x1p-31);   // hi as an integer-valued double, |t| < 2^60
+    const double lo = w - t * 0x1p31;       // exact, in [0, 2^31)
+    const double th = floor(t * 0x1p-32);
+    const double tl = t - th * 0x1p32;      // exact, in [0, 2^32)
+    const unsigned long long hi =
+        ((unsigned long long)(long long)(int)th << 32) | (unsigned long long)(unsigned)tl;
+    atomicAdd((unsigned long long*)p, hi);
+    atomicAdd((unsigned long long*)p + 1, (unsigned long long)(unsigned)lo);
+}
+
+// Value of element i of a J'/K' buffer of fixed-point limb pairs
+// (inv = 2^-S).
+__device__ __forceinline__ double partial_value(const double* A, long long i, double inv)
+{
+    const long long hi = ((const long long*)A)[2 * i];
+    const long long lo = ((const long long*)A)[2 * i + 1];
+    return fma((double)hi, 0x1p31, (double)lo) * inv;
+}
+
+// Flush one partial sum into J' / K' (element index from jidx / kidx, below
+// 2^31 by the build's size check, so 2 idx fits 32 unsigned bits).
+__device__ __forceinline__ void acc_j(const MolView& mc, int idx, double v)
+{
+    fx_add(mc.J + 2u * (unsigned)idx, v, mc.fxs);
+}
+__device__ __forceinline__ void acc_k(const MolView& mc, int idx, double v)
+{
+    fx_add(mc.K + 2u * (unsigned)idx, v, mc.fxs);
 }
 
 __device__ __forceinline__ double wave_max(double v)
@@ -267,24 +318,6 @@ __device__ __forceinline__ float red_if(float v)
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
     return v;
-}
-
-// Per wave step, one atomic per wave: the FP64 kernel counts the quartets it
-// evaluates (slot 0) and those removed by screening (slot 2); the FP32
-// kernel counts the quartets it evaluates (slot 1).
-__device__ __forceinline__ void route_count(const Digest& dg, bool valid, bool active, bool use32, bool f32)
-{
-    if (!dg.counts) return;
-    const unsigned long long nv = __popcll(__ballot(valid));
-    const unsigned long long na = __popcll(__ballot(active));
-    if (threadIdx.x == 0) {
-        if (f32) {
-            if (use32 && na) atomicAdd(dg.counts + 1, na);
-        } else {
-            if (!use32 && na) atomicAdd(dg.counts, na);
-            if (nv > na) atomicAdd(dg.counts + 2, nv - na);
-        }
-    }
 }
 
 __device__ __forceinline__ double wave_sum(double v)

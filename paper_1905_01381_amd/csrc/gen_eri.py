@@ -357,11 +357,13 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
     for i in range(na):
         for j in range(nb):
             s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s})); if (dj == 0 && rowv) atomic_add(mc.J + jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s}));")
+            out(f"      if (dg.acc_lvl) {{ if (dj == 0) s_jab[(m * {na * nb} + {i * nb + j}) * 8 + bi] += s; }}")
+            out(f"      else if (dj == 0 && rowv) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     for k in range(nc):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xab{i}{j}" for i in range(na) for j in range(nb))
-            out(f"    {{ const {T_()} s = {red('red_i')}({lit(2)} * ({s})); if (bi == 0 && colv) atomic_add(mc.J + jidx(dg, mc, fc + {k}, fd + {l}, js), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({lit(2)} * ({s})); if (bi == 0 && colv) acc_j(mc, jidx(dg, mc, fc + {k}, fd + {l}, js), s); }}")
     out("  }")
     out("  if (ks >= 0) {")
     for j in range(nb):
@@ -379,23 +381,26 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
     for i in range(na):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xbd{j}{l}" for j in range(nb) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_i')}({red('red_j')}({s})); if (lane == 0) atomic_add(mc.K + kidx(dg, mc, fa + {i}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({red('red_j')}({s})); if (lane == 0) acc_k(mc, kidx(dg, mc, fa + {i}, fc + {k}, ks), s); }}")
     for i in range(na):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
-            out(f"    {{ const {T_()} s = {red('red_i')}({s}); if (bi == 0 && colv) atomic_add(mc.K + kidx(dg, mc, fa + {i}, fd + {l}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_i')}({s});")
+            out(f"      if (dg.acc_lvl) {{ if (bi == 0) s_kad[(m * {na * nd} + {i * nd + l}) * 8 + dj] += s; }}")
+            out(f"      else if (bi == 0 && colv) acc_k(mc, kidx(dg, mc, fa + {i}, fd + {l}, ks), s); }}")
     for j in range(nb):
         for k in range(nc):
             s = " + ".join(f"{V(i, j, k, l)} * xad{i}{l}" for i in range(na) for l in range(nd))
-            out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fc + {k}, ks), s); }}")
+            out(f"    {{ const {T_()} s = {red('red_j')}({s}); if (dj == 0 && rowv) acc_k(mc, kidx(dg, mc, fb + {j}, fc + {k}, ks), s); }}")
     # K'_bd does not depend on c: it accumulates per lane in LDS over the
-    # task's c range and is flushed once per task (acc_flush)
+    # task's c range and is flushed once per task (acc_flush); J'_ab and K'_ad
+    # (above) likewise, one entry per row / column
     for j in range(nb):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
             out(f"    {{ const {T_()} s = {s};")
-            out(f"      if (dg.acc_direct) {{ if (active) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
-            out(f"      else s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane] += s; }}")
+            out(f"      if (dg.acc_lvl < 2) {{ if (active) acc_k(mc, kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
+            out(f"      else s_kbd[(m * {nb * nd} + {j * nd + l}) * 64 + lane] += s; }}")
     out("  }")
     out("}")
 
@@ -430,9 +435,14 @@ STAGE_CFG = {
 # of spill outside the primitive loop).  (ps|ps) goes from 2 to 3 waves and
 # (ps|ss) from 3 to 4, 17 % and 8 % faster on MI355X; (pp|ss) at 3 waves
 # was slower, and classes further from a step spill inside the loop.
+# (ss|ss) and (ds|ps) sit a few registers above 5 and 2 waves with the
+# fixed-point flushes and the LDS task accumulators ((pp|ps) at 2 waves
+# spilled inside the loop and was slower).
 UNSTAGED_WAVES = {
+    (0, 0, 0, 0): 5,
     (1, 0, 1, 0): 3,
     (1, 0, 0, 0): 4,
+    (2, 0, 1, 0): 2,
 }
 
 
@@ -725,7 +735,7 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
                 elif rd != "none":
                     val = f"{red(rd)}({val})"
                 out(f"    {{ const {T_()} s = {val};")
-                out(f"      if ({guard}) atomic_add(mc.{arr} + {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s); }}")
+                out(f"      if ({guard}) acc_{arr.lower()}(mc, {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s); }}")
             out("  }")
             out("}")
 
@@ -746,39 +756,66 @@ HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 
 def acc_doubles(la, lb, lc, ld):
     """LDS doubles per density slot for the task accumulator of K'_bd (one
-    per lane and element; unstaged classes only).  K'_ad and J'_ab are
-    task-invariant too, but they take one atomic per eight lanes only and
-    accumulating them in LDS measured no faster."""
+    per lane and element; unstaged classes only)."""
     return 0 if is_staged(la, lb, lc, ld) else 64 * ncart(lb) * ncart(ld)
+
+
+def acc8_doubles(la, lb, lc, ld):
+    """LDS doubles per density slot for the task accumulators of J'_ab (one
+    per wave row) and K'_ad (one per wave column); unstaged classes only."""
+    return 0 if is_staged(la, lb, lc, ld) else 8 * (ncart(la) * ncart(lb) + ncart(la) * ncart(ld))
 
 
 def emit_acc_zero(o: Emitter, la, lb, lc, ld):
     """Each accumulator entry is zeroed, summed and flushed by its own lane,
     so no cross-lane ordering is needed."""
     kbd = acc_doubles(la, lb, lc, ld) // 64
-    o("    if (!dg.acc_direct)")
+    nab, nad = ncart(la) * ncart(lb), ncart(la) * ncart(ld)
+    o("    if (dg.acc_lvl >= 2)")
     o(f"      for (int t = 0; t < {kbd} * dg.nX; ++t) s_kbd[t * 64 + lane] = 0.0;")
+    o("    if (dg.acc_lvl) {")
+    o(f"      if (dj == 0) for (int t = 0; t < {nab} * dg.nX; ++t) s_jab[t * 8 + bi] = 0.0;")
+    o(f"      if (bi == 0) for (int t = 0; t < {nad} * dg.nX; ++t) s_kad[t * 8 + dj] = 0.0;")
+    o("    }")
 
 
 def emit_acc_flush(o: Emitter, la, lb, ld):
-    """Once per task: add the LDS accumulator to K'."""
-    nb, nd = ncart(lb), ncart(ld)
-    o("    if (!dg.acc_direct && rowv && dval && fdv >= 0) {")
+    """Once per task: add the LDS accumulators to J' and K'."""
+    na, nb, nd = ncart(la), ncart(lb), ncart(ld)
+    o("    if (dg.acc_lvl) {")
+    o("      for (int m = 0; m < dg.nX; ++m) {")
+    o("        const int js = dg.jslot[m], ks = dg.kslot[m];")
+    o("        if (js >= 0 && dj == 0 && rowv) {")
+    for i in range(na):
+        for j in range(nb):
+            o(f"          {{ const double s = s_jab[(m * {na * nb} + {i * nb + j}) * 8 + bi];")
+            o(f"            if (s != 0.0) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
+    o("        }")
+    o("        if (ks >= 0 && bi == 0 && fdv >= 0) {")
+    for i in range(na):
+        for l in range(nd):
+            o(f"          {{ const double s = s_kad[(m * {na * nd} + {i * nd + l}) * 8 + dj];")
+            o(f"            if (s != 0.0) acc_k(mc, kidx(dg, mc, fa + {i}, fdv + {l}, ks), s); }}")
+    o("        }")
+    o("      }")
+    o("    }")
+    o("    if (dg.acc_lvl >= 2 && rowv && dval && fdv >= 0) {")
     o("      for (int m = 0; m < dg.nX; ++m) {")
     o("        const int ks = dg.kslot[m];")
     o("        if (ks < 0) continue;")
     for j in range(nb):
         for l in range(nd):
-            o(f"        {{ const double s = s_kbd[({j * nd + l} * dg.nX + m) * 64 + lane];")
-            o(f"          if (s != 0.0) atomic_add(mc.K + kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
+            o(f"        {{ const double s = s_kbd[(m * {nb * nd} + {j * nd + l}) * 64 + lane];")
+            o(f"          if (s != 0.0) acc_k(mc, kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
     o("      }")
     o("    }")
 
 
 def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
-    """One J/K kernel of a class in one precision.  Both kernels of a class
-    walk the same tasks and take the same per-step routing decision; each
-    evaluates only the steps of its own precision."""
+    """One J/K kernel of a class in one precision.  Without screening or
+    routing the FP64 kernel walks every task; otherwise each kernel walks the
+    task list and step masks of its own precision that the build's
+    classification pass wrote."""
     cn = class_name(la, lb, lc, ld)
     L = la + lb + lc + ld
     staged = is_staged(la, lb, lc, ld)
@@ -812,7 +849,12 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     emit_boys_lds(o, L, f32)
     kbd = acc_doubles(la, lb, lc, ld)
     if kbd:
-        o("  extern __shared__ double s_kbd[];  // K'_bd accumulator [kbd][nX][64 lanes], sized at launch")
+        # task accumulators, sized at launch: K'_bd [nbd][nX][64 lanes] (level 2),
+        # then J'_ab [nab][nX][8 rows] and K'_ad [nad][nX][8 columns] (level >= 1)
+        o("  extern __shared__ double s_acc[];")
+        o(f"  double* const s_kbd = s_acc;")
+        o(f"  double* const s_jab = s_acc + (dg.acc_lvl >= 2 ? {kbd} * dg.nX : 0);")
+        o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * 8} * dg.nX;")
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
     if staged:
@@ -820,7 +862,14 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("  const int svo = lane * 8;")
         o("#define STL(i) stage_load(srs, svo, (i))")
         o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
-    o("  for (int task = blockIdx.x; task < tm.ntask; task += gridDim.x) {")
+    # With screening or routing, the build's classification pass lists the
+    # tasks that have steps of this kernel's precision and marks those steps
+    # (bit c - c_lo of the task's mask); the kernel walks only them.
+    o("  const bool listed = tm.list != nullptr;")
+    o("  const int ntk = listed ? *tm.list_n : tm.ntask;")
+    o("  for (int it = blockIdx.x; it < ntk; it += gridDim.x) {")
+    o("    const int task = listed ? tm.list[it] : it;")
+    o(f"    const unsigned long long smask = listed ? tm.masks[2 * task + {1 if f32 else 0}] : ~0ull;")
     o("    const int4 tk = tm.tasks[task];")
     o("    const int4 tk2 = tm.tasks2[task];")
     o("    const MolView mc = mol_view(dg, tm, tk2.z);")
@@ -840,6 +889,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         emit_acc_zero(o, la, lb, lc, ld)
         o("    int fdv = -1;  // first function of d (valid once a step with this d ran)")
     o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
+    o("      if (!((smask >> (c_idx - c_lo)) & 1ull)) continue;")
     o("      const int c = tm.shl_c[c_idx];")
     o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
     o("      bool active = rowv && colv;")
@@ -849,17 +899,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
     if kbd:
         o("      if (colv) fdv = fd;")
-    o("      const bool valid = active;")
-    o("      double bnd = 0.0;")
-    o("      if (dg.mode != 0 || dg.skip > 0.0) bnd = quartet_bound(mc, bra.Q[ib], ket.Q[jk], a, b, c, d);")
-    o("      if (dg.skip > 0.0 && active) active = bnd >= dg.skip;")
-    o("      const bool use32 = dg.mode == 1 && wave_max(active ? bnd : 0.0) < dg.fp32_below;")
-    if f32:
-        o("      route_count(dg, valid, active, use32, true);")
-        o("      if (!use32) continue;")
-    else:
-        o("      route_count(dg, valid, active, use32, false);")
-        o("      if (use32) continue;")
+    o("      if (dg.skip > 0.0 && active) active = quartet_bound(mc, bra.Q[ib], ket.Q[jk], a, b, c, d) >= dg.skip;")
     o("      if (!__any(active)) continue;")
     if ld > 0:
         o(f"      const {t} CDx = ket.ABx[jk], CDy = ket.ABy[jk], CDz = ket.ABz[jk];")
@@ -889,11 +929,22 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     return o.text(), nvrr, stage_n
 
 
+# Classes also generated with bra and ket exchanged, (lc ld|la lb): the same
+# unique quartets with the wave's loop running over the other pair's first
+# shell.  A step's flushes are J'_cd, K'_ac and K'_bc (eight rows of K'_bc
+# per step); exchanged, K'_bc becomes the original K'_ad, so for classes
+# with ncart(la) ncart(ld) < ncart(lb) ncart(lc) the exchange flushes fewer
+# exchange partial sums per step.  The build picks an orientation per class
+# (cq_autotune times both).
+SWAP_CLASSES = [(1, 1, 1, 0), (2, 1, 1, 0), (2, 1, 2, 0), (2, 2, 1, 0)]
+
+
 def gen(lmax: int) -> dict:
     pcls, classes = all_classes(lmax)
     files = {}
     stats = []
     stage_sizes = {}
+    swapped = {}
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
@@ -906,6 +957,11 @@ def gen(lmax: int) -> dict:
         o('#include "eri_common.hpp"')
         o("")
         o.lines.append(k64)
+        if (la, lb, lc, ld) in SWAP_CLASSES and (la, lb, lc, ld) in classes:
+            s64, _, _ = emit_jk_kernel(lc, ld, la, lb, "double")
+            s32, _, _ = emit_jk_kernel(lc, ld, la, lb, "float")
+            o.lines.append(s64)
+            swapped[(la, lb, lc, ld)] = s32
         # block kernel (tests and Schwarz): quartet list -> raw blocks, FP64
         body2 = Emitter("  ")
         emit_eri_body(body2, la, lb, lc, ld)
@@ -929,6 +985,8 @@ def gen(lmax: int) -> dict:
         o('#include "eri_common.hpp"')
         o("")
         o.lines.append(k32)
+        if (la, lb, lc, ld) in swapped:
+            o.lines.append(swapped[(la, lb, lc, ld)])
         files[f"eri_{cn}_f32.hip"] = o.text() + "\n"
     o = Emitter("")
     o(HEADER)
@@ -939,15 +997,26 @@ def gen(lmax: int) -> dict:
         o(f"__global__ void eri_jk_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
         o(f"__global__ void eri_jk32_{cn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
         o(f"__global__ void eri_block_{cn}(const PairSet bra, const PairSet ket, const int* __restrict__ qlist, int nq, double* __restrict__ out, const double* __restrict__ boys_tab);")
+        if (la, lb, lc, ld) in swapped:
+            sn = class_name(lc, ld, la, lb)
+            o(f"__global__ void eri_jk_{sn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
+            o(f"__global__ void eri_jk32_{sn}(const PairSet bra, const PairSet ket, const TaskMap tm, const Digest dg, const double* __restrict__ boys_tab);")
     # dispatch tables
     o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); };")
+    o("// jks / jk32s: the kernels of the exchanged orientation (lc ld|la lb), or NULL; acc_s / acc8_s their")
+    o("// LDS accumulator sizes")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; int acc8; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); eri_jk_fn jks; eri_jk_fn jk32s; int acc_s, acc8_s; };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
         cn = class_name(la, lb, lc, ld)
         nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}}},")
+        if (la, lb, lc, ld) in swapped:
+            sn = class_name(lc, ld, la, lb)
+            sw = f"eri_jk_{sn}, eri_jk32_{sn}, {acc_doubles(lc, ld, la, lb)}, {acc8_doubles(lc, ld, la, lb)}"
+        else:
+            sw = "nullptr, nullptr, 0, 0"
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, {acc8_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}, {sw}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)

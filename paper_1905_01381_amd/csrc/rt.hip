@@ -12,15 +12,20 @@
 //       corrects the previous step's propagator applied to P_k (see the
 //       proposal section below); when (P_k + P_{k+1})/2 reproduces it within
 //       the acceptance tolerance the step costs one build, otherwise the
-//       self-consistent iteration of mode 1 continues from there.
+//       self-consistent iteration of mode 1 continues from there.  Mode 1
+//       applies the same first-iterate acceptance to its extrapolated guess,
+//       so both modes are judged at one tolerance.
+//   mode 3 (MMUT, the paper's default leap-frog integrator):
+//       P_{k+1} = U P_{k-1} U^dagger, U = exp(-2 i dt F'(P_k))  -> 1 build;
+//       the first step and every `restart`-th step are EM2 steps from P_k
+//       (the paper's seed and restart step).
 // The matrix exponential is a Taylor series with scaling and squaring
-// (paper: exponential by Taylor/Chebyshev series); every dense product is a
-// rocBLAS ZGEMM.  Expectation values follow Eq. td_expectation with the
+// (paper: exponential by Taylor/Chebyshev series); every dense product is the
+// library's complex GEMM on the FP64 matrix cores (k_zgemm).  Expectation values follow Eq. td_expectation with the
 // closed-shell spin factor 2.
 #include "cq.h"
 #include "eri_common.hpp"
 
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -37,11 +42,6 @@ cq_status cq_internal_fail(cq_status s, const char* msg);
     do {                                                                                       \
         hipError_t e_ = (x);                                                                   \
         if (e_ != hipSuccess) return cq_internal_fail(CQ_EHIP, hipGetErrorString(e_));        \
-    } while (0)
-#define BLASCHK(x)                                                                             \
-    do {                                                                                       \
-        rocblas_status s_ = (x);                                                               \
-        if (s_ != rocblas_status_success) return cq_internal_fail(CQ_EHIP, "rocBLAS call failed"); \
     } while (0)
 
 namespace {
@@ -420,6 +420,78 @@ __global__ void k_fill_f(float* p, int n, float v)
     if (i < n) p[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Complex GEMM on the FP64 matrix cores: C = alpha A op(B) + beta C for
+// row-major complex n x n matrices (interleaved re, im), op(B) = B or B^H.
+// A workgroup of four waves computes a 32 x 32 tile of C, each wave one
+// 16 x 16 block as four real products (Re Re, Im Im, Re Im, Im Re) with
+// V_MFMA_F64_16X16X4_F64; K advances in chunks of 16 staged through LDS.
+// Operand lanes: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k;
+// lane l holds D[l / 16 + 4 v][l % 16], v = 0..3 (measured on gfx950).
+// Out-of-range rows, columns and k are zero-padded in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kGT = 32, kGK = 16;
+typedef double gemm_v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_zgemm(int n, const double2* __restrict__ A, const double2* __restrict__ B,
+                                               int conjB, double2 alpha, double2 beta, double2* __restrict__ C)
+{
+    __shared__ double2 sA[kGT][kGK + 1];
+    __shared__ double2 sB[kGK][kGT + 1];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+    gemm_v4d rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+        for (int e = tid; e < kGT * kGK; e += 256) {
+            {
+                const int i = e / kGK, k = e % kGK;  // A row i, column k (k fastest: coalesced)
+                const int gr = r0 + i, gk = k0 + k;
+                sA[i][k] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : make_double2(0.0, 0.0);
+            }
+            if (conjB) {
+                const int j = e / kGK, kb = e % kGK;  // op(B)[kb][j] = conj(B[j][kb]) (kb fastest)
+                const int gc = c0 + j, gk = k0 + kb;
+                double2 v = make_double2(0.0, 0.0);
+                if (gc < n && gk < n) {
+                    const double2 t = B[(size_t)gc * n + gk];
+                    v = make_double2(t.x, -t.y);
+                }
+                sB[kb][j] = v;
+            } else {
+                const int kb = e / kGT, j = e % kGT;  // B row kb, column j (j fastest)
+                const int gk = k0 + kb, gc = c0 + j;
+                sB[kb][j] = (gk < n && gc < n) ? B[(size_t)gk * n + gc] : make_double2(0.0, 0.0);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 4) {
+            const double2 a = sA[wr + (l & 15)][kk + (l >> 4)];
+            const double2 b = sB[kk + (l >> 4)][wc + (l & 15)];
+            rr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, rr, 0, 0, 0);
+            ii = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, ii, 0, 0, 0);
+            ri = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ri, 0, 0, 0);
+            ir = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ir, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int gr = r0 + wr + (l >> 4) + 4 * v, gc = c0 + wc + (l & 15);
+        if (gr < n && gc < n) {
+            const double re = rr[v] - ii[v], im = ri[v] + ir[v];
+            double2 o = make_double2(alpha.x * re - alpha.y * im, alpha.x * im + alpha.y * re);
+            if (beta.x != 0.0 || beta.y != 0.0) {
+                const double2 c = C[(size_t)gr * n + gc];
+                o.x += beta.x * c.x - beta.y * c.y;
+                o.y += beta.x * c.y + beta.y * c.x;
+            }
+            C[(size_t)gr * n + gc] = o;
+        }
+    }
+}
+
 dim3 grid1(long long n)
 {
     long long g = (n + 255) / 256;
@@ -436,7 +508,6 @@ struct cq_rt_s {
     int n = 0;
     double dt = 0;
     int mode = 0;
-    rocblas_handle blas = nullptr;
     hipStream_t stream = nullptr;
     double2 *Xc = nullptr, *Dc = nullptr;       // S^-1/2 and dipole operator as complex
     double *h = nullptr, *Dz = nullptr;         // AO core Hamiltonian and dipole (real)
@@ -447,8 +518,9 @@ struct cq_rt_s {
     bool have_u = false;
     double *re = nullptr, *im = nullptr, *J = nullptr, *Kr = nullptr, *Ki = nullptr, *red = nullptr;
     int nhist = 1;  // densities available in hist
-    double sc_tol = 1e-10, acc_tol = 1e-8;
+    double sc_tol = 1e-10, acc_tol = 1e-10;
     int max_iter = 30;
+    int restart = 1000;  // MMUT: EM2 restart period (steps)
     long long steps = 0, builds = 0, accepted = 0, fallbacks = 0;
     // MLP
     float *w = nullptr, *gw = nullptr, *am = nullptr, *av = nullptr, *xs = nullptr, *lossd = nullptr;
@@ -473,15 +545,15 @@ static cq_status rt_alloc(cq_rt_s* r, T** p, size_t count)
     return CQ_OK;
 }
 
-// row-major C = A op(B): column-major C^T = op(B)^T A^T
+// row-major C = alpha A op(B) + beta C on the matrix cores (C must not
+// alias A or B)
 static cq_status mm(cq_rt_s* r, double2* C, const double2* A, const double2* B, bool conjB, double2 alpha = {1.0, 0.0},
                     double2 beta = {0.0, 0.0})
 {
     const int n = r->n;
-    BLASCHK(rocblas_zgemm(r->blas, conjB ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
-                          rocblas_operation_none, n, n, n, (const rocblas_double_complex*)&alpha,
-                          (const rocblas_double_complex*)B, n, (const rocblas_double_complex*)A, n,
-                          (const rocblas_double_complex*)&beta, (rocblas_double_complex*)C, n));
+    const dim3 grid((n + kGT - 1) / kGT, (n + kGT - 1) / kGT);
+    hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, r->stream, n, A, B, conjB ? 1 : 0, alpha, beta, C);
+    RTCHK(hipGetLastError());
     return CQ_OK;
 }
 
@@ -607,9 +679,9 @@ static cq_status midpoint_iterate(cq_rt_s* r, bool learned)
         hipLaunchKernelGGL(k_axpby, grid1(nn), dim3(256), 0, r->stream, r->Pguess, r->hist[0], 0.5, 0.5, nn);
         double d = 0;
         if ((st = maxdiff(r, r->Pguess, r->Pmid, &d))) return st;
-        const double tol = (learned && it == 0) ? r->acc_tol : r->sc_tol;
-        if (learned && it == 0 && d < tol) r->accepted++;
-        if (learned && it == 0 && !(d < tol)) r->fallbacks++;
+        const double tol = it == 0 ? r->acc_tol : r->sc_tol;
+        if (it == 0 && d < tol) r->accepted++;
+        if (it == 0 && !(d < tol)) r->fallbacks++;
         std::swap(r->Pmid, r->Pguess);
         if (d < tol) break;
         if (it == r->max_iter - 1) return cq_internal_fail(CQ_ENOTCONV, "midpoint iteration did not converge");
@@ -647,6 +719,19 @@ static cq_status step_mid(cq_rt_s* r, bool learned)
                            r->Pmid, nn);
     hipLaunchKernelGGL(k_hermitize, grid1(nn), dim3(256), 0, r->stream, r->Pmid, r->n);
     return midpoint_iterate(r, learned);
+}
+
+// MMUT leap-frog step from P_{k-1} (hist[1]) with the Fock matrix of P_k
+// (hist[0]); EM2 for the seed step and every restart-th step.
+static cq_status step_mmut(cq_rt_s* r)
+{
+    if (r->nhist < 2 || r->steps % r->restart == 0) return step_em2(r);
+    cq_status st;
+    if ((st = fock(r, r->hist[0], r->Fo))) return st;
+    if ((st = expm(r, r->Fo, 2.0 * r->dt, r->U))) return st;
+    if ((st = transform(r, r->U, r->hist[1], r->Pnext))) return st;
+    push_history(r, r->Pnext);
+    return CQ_OK;
 }
 
 // Dipole -2 Re Tr(D_z P) of the newest density; with want_energy also the
@@ -687,7 +772,8 @@ extern "C" cq_status cq_rt_create(cq_basis b, const double* h, const double* X, 
     *out = nullptr;
     if (!b || !h || !X || !Dz || !P0) return cq_internal_fail(CQ_EINVAL, "NULL argument");
     if (!(dt > 0) || !std::isfinite(dt)) return cq_internal_fail(CQ_EINVAL, "dt must be positive");
-    if (mode < 0 || mode > 2) return cq_internal_fail(CQ_EINVAL, "mode must be 0 (EM2), 1 (midpoint) or 2 (learned)");
+    if (mode < 0 || mode > 3)
+        return cq_internal_fail(CQ_EINVAL, "mode must be 0 (EM2), 1 (midpoint), 2 (learned) or 3 (MMUT)");
     if (cq_basis_nmol(b) != 1) return cq_internal_fail(CQ_EUNSUPPORTED, "real-time propagation takes a single-molecule basis");
     cq_rt_s* r = new cq_rt_s();
     r->b = b;
@@ -698,11 +784,6 @@ extern "C" cq_status cq_rt_create(cq_basis b, const double* h, const double* X, 
     const int n = r->n;
     const long long nn = (long long)n * n;
     cq_status st = CQ_OK;
-    if (rocblas_create_handle(&r->blas) != rocblas_status_success) {
-        delete r;
-        return cq_internal_fail(CQ_EHIP, "rocblas_create_handle failed");
-    }
-    rocblas_set_stream(r->blas, stream);
     double2** cbufs[] = {&r->Xc, &r->Dc, &r->hist[0], &r->hist[1], &r->hist[2], &r->hist[3], &r->Pmid, &r->Pnext,
                          &r->Pguess, &r->Fo, &r->Fo2, &r->A, &r->U, &r->T1, &r->T2, &r->Pao, &r->Fao, &r->Uprev,
                          &r->Pbase};
@@ -760,7 +841,6 @@ extern "C" cq_status cq_rt_destroy(cq_rt r)
     (void)hipDeviceSynchronize();
     for (void* p : r->owned) (void)hipFree(p);
     if (r->rec_idx) (void)hipFree(r->rec_idx);
-    if (r->blas) rocblas_destroy_handle(r->blas);
     delete r;
     return CQ_OK;
 }
@@ -777,8 +857,15 @@ extern "C" cq_status cq_rt_set_params(cq_rt r, double sc_tol, int max_iter, doub
 
 extern "C" cq_status cq_rt_set_mode(cq_rt r, int mode)
 {
-    if (!r || mode < 0 || mode > 2) return cq_internal_fail(CQ_EINVAL, "bad mode");
+    if (!r || mode < 0 || mode > 3) return cq_internal_fail(CQ_EINVAL, "bad mode");
     r->mode = mode;
+    return CQ_OK;
+}
+
+extern "C" cq_status cq_rt_set_restart(cq_rt r, int period)
+{
+    if (!r || period < 1) return cq_internal_fail(CQ_EINVAL, "restart period must be >= 1");
+    r->restart = period;
     return CQ_OK;
 }
 
@@ -789,6 +876,7 @@ extern "C" cq_status cq_rt_step(cq_rt r, int nsteps, double* energy, double* dip
         const long long b0 = r->builds;
         cq_status st;
         if (r->mode == 0) st = step_em2(r);
+        else if (r->mode == 3) st = step_mmut(r);
         else st = step_mid(r, r->mode == 2);
         if (st) return st;
         r->steps++;
@@ -937,8 +1025,6 @@ extern "C" cq_status cq_expm(int n, const double* H, double dt, double* U, hipSt
     cq_rt_s r;
     r.n = n;
     r.stream = stream;
-    if (rocblas_create_handle(&r.blas) != rocblas_status_success) return cq_internal_fail(CQ_EHIP, "rocblas handle");
-    rocblas_set_stream(r.blas, stream);
     const long long nn = (long long)n * n;
     cq_status st = CQ_OK;
     if (!st) st = rt_alloc(&r, &r.A, nn);
@@ -948,7 +1034,6 @@ extern "C" cq_status cq_expm(int n, const double* H, double dt, double* U, hipSt
     if (!st) st = expm(&r, (const double2*)H, dt, (double2*)U);
     (void)hipStreamSynchronize(stream);
     for (void* p : r.owned) (void)hipFree(p);
-    rocblas_destroy_handle(r.blas);
     return st;
 }
 
@@ -970,4 +1055,16 @@ extern "C" cq_status cq_mlp_adam(float* w, const float* g, float* m, float* v, f
     hipLaunchKernelGGL(k_adam, dim3(2), dim3(256), 0, stream, w, g, m, v, kMlpParams, lr, 0.9f, 0.999f, 1e-8f, step);
     RTCHK(hipGetLastError());
     return CQ_OK;
+}
+
+// C = A op(B) (row-major complex n x n on the device; op = conjugate
+// transpose when conjB), the GEMM every real-time product uses.
+extern "C" cq_status cq_zgemm(int n, const double* A, const double* B, int conjB, double* C, hipStream_t stream)
+{
+    if (n < 1 || !A || !B || !C) return cq_internal_fail(CQ_EINVAL, "bad arguments");
+    if (C == A || C == B) return cq_internal_fail(CQ_EINVAL, "C must not alias A or B");
+    cq_rt_s r;
+    r.n = n;
+    r.stream = stream;
+    return mm(&r, (double2*)C, (const double2*)A, (const double2*)B, conjB != 0);
 }

@@ -40,7 +40,9 @@ def test_argument_errors_without_gpu_work():
     assert st == cq.CQ_EINVAL
     assert b"nshell" in L.cq_last_error()
     assert L.cq_jk_build(None, 1, None, None, None, None, None, None) == cq.CQ_EINVAL
-    assert L.cq_boys(99, 1, None, None, None) == cq.CQ_EINVAL
+    assert L.cq_boys(99, 1, None, None, 0, None) == cq.CQ_EINVAL
+    assert L.cq_boys(3, 1, None, None, 2, None) == cq.CQ_EINVAL
+    assert L.cq_sync_status(None, None) == cq.CQ_EINVAL
     assert L.cq_basis_nbf(None) == -1
     assert L.cq_basis_nmol(None) == -1
     assert L.cq_basis_create_batch(0, None, None, None, None, None, None, None, ctypes.byref(h)) == cq.CQ_EINVAL
@@ -48,3 +50,31 @@ def test_argument_errors_without_gpu_work():
     assert L.cq_basis_create_batch(2, ns, None, None, None, None, None, None, ctypes.byref(h)) == cq.CQ_EINVAL
     assert b"molecule 1" in L.cq_last_error()
     assert L.cq_autotune(None, 1, 1, None) == cq.CQ_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcq.so not built")
+def test_size_check_guards_32bit_offsets():
+    """The kernels address a molecule's [nbf][nbf][slots] blocks with 32-bit
+    offsets; builds that would overflow them are refused before any work
+    (checked on the host, no GPU)."""
+    from paper_1905_01381_amd import cq
+    assert cq.jk_size_check(600, 8, 1, 8) == cq.CQ_OK
+    assert cq.jk_size_check(3000, 16, 16, 16) == cq.CQ_OK
+    assert cq.jk_size_check(16383, 8, 8, 8) == cq.CQ_OK          # 2.147e9 - 8 * 32767 < 2^31
+    assert cq.jk_size_check(16384, 8, 8, 8) == cq.CQ_EUNSUPPORTED  # exactly 2^31
+    assert cq.jk_size_check(11586, 16, 1, 1) == cq.CQ_EUNSUPPORTED  # 16 slots above 11585 functions
+    assert cq.jk_size_check(11585, 1, 16, 1) == cq.CQ_OK
+    assert cq.jk_size_check(11586, 1, 1, 16) == cq.CQ_EUNSUPPORTED
+    assert b"2^31" in cq.lib().cq_last_error()
+    assert cq.jk_size_check(-1, 1, 1, 1) == cq.CQ_EINVAL
+    # every (nbf, slots) pair agrees with the 64-bit product
+    for nbf in (1, 4095, 11585, 11586, 16383, 16384, 46340, 46341):
+        for w in (1, 2, 8, 9, 16):
+            want = cq.CQ_OK if nbf * nbf * w < 2 ** 31 else cq.CQ_EUNSUPPORTED
+            assert cq.jk_size_check(nbf, w, 1, 1) == want, (nbf, w)
+
+
+def test_thresholds_flags():
+    from paper_1905_01381_amd import cq
+    assert cq.thresholds().flags == cq.CQ_DETERMINISTIC
+    assert cq.thresholds(accumulate=True).flags == cq.CQ_DETERMINISTIC | cq.CQ_ACCUMULATE

@@ -1,0 +1,363 @@
+"""GPU parity on the workload recipes and the boundary's status paths.
+
+* The mixed-precision workload's recipe (3s2p1d, exponents 0.1..1e3): a
+  6-atom molecule against the full oracle J/K (FP64 at 1e-10; routed at the
+  configured thresholds, skip 1e-11 and FP32 below 1e-5, within 1e-6 Eh);
+  a 60-atom molecule (nbf 900) on sampled oracle blocks, FP64 and routed.
+* The real-time workload's recipe (nuclear charge 1, 3s2p1d): one EM2 step
+  from an oracle ground state against the oracle's EM2.
+* The self-consistent midpoint corrector against the oracle's midpoint step.
+* The FP32 Boys function of the routed kernels against the oracle.
+* Screening: every element's change stays within the sum of the bounds of
+  the quartets that were skipped (bounds recomputed on the host).
+* Deterministic accumulation: builds are bitwise repeatable.
+* A non-finite density element is reported by cq_sync_status.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rt, scf, twocomp
+from paper_1905_01381_amd import inputs
+from tests.gpu_common import case_2c, case_real, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_JK = 1e-10
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.name}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1905_01381_amd import cq
+    cq.lib()
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _jk(torch, gb, mats, sym=None, th=None, want_j=True, want_k=True):
+    r = gb.jk([_dev(torch, m) for m in mats], sym=sym, th=th, want_j=want_j, want_k=want_k)
+    torch.cuda.synchronize()
+    return ([j.cpu().numpy() if j is not None else None for j in r.J],
+            [k.cpu().numpy() if k is not None else None for k in r.K])
+
+
+def _energy(P, J, K):
+    return 2.0 * float(np.sum(P * J)) - float(np.sum(P * K))
+
+
+# ------------------------------------------------------------------ Boys FP32
+def test_boys_fp32_against_oracle(torch_cuda):
+    """The FP32 evaluation the routed kernels use: relative error within
+    2e-6 of the FP64 oracle (FP32 table and recursion below T = 36 and order
+    6; FP64 rounded to FP32 elsewhere)."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    T = np.concatenate([[0.0, 1e-7, 0.25, 0.5, 17.3, 35.99, 36.0, 36.5, 60.0, 500.0],
+                        np.random.default_rng(4).uniform(0, 45, 600)])
+    T32 = T.astype(np.float32).astype(np.float64)   # the kernels round T to FP32 first
+    worst = 0.0
+    for mmax in (0, 2, 5, 8):
+        F = cq.boys(mmax, _dev(torch, T), fp32=True).cpu().numpy()
+        ref = oracle.boys_table(mmax, T32)
+        err = np.abs(F - ref) / np.abs(ref)
+        worst = max(worst, float(err.max()))
+        assert err.max() < 2e-6, (mmax, err.max(), T[np.unravel_index(err.argmax(), err.shape)[0]])
+        F64 = cq.boys(mmax, _dev(torch, T)).cpu().numpy()
+        assert np.abs(F64 - oracle.boys_table(mmax, T)).max() < 1e-13 * np.abs(F64).max()
+    print(f"FP32 Boys: worst relative error {worst:.2e}", flush=True)
+
+
+# ------------------------------------------------------------------ status
+def test_nonfinite_density_reported(torch_cuda):
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, P = case_real(2, inputs.SHELLS_2S1P, seed=3, lo=0.15, hi=30.0)
+    gb = cq.Basis.from_molecule(w.mol)
+    assert gb.sync_status() == cq.CQ_OK
+    bad = P.copy()
+    bad[1, 2] = np.nan
+    _jk(torch, gb, [P, bad], sym=[1, 1])
+    assert gb.sync_status() == cq.CQ_ENONFINITE
+    assert b"non-finite" in cq.lib().cq_last_error()
+    assert gb.sync_status() == cq.CQ_OK          # reading clears the word
+    _jk(torch, gb, [P])
+    assert gb.sync_status() == cq.CQ_OK
+    w2, ob2, P2 = case_2c(2, inputs.SHELLS_2S1P, seed=5, lo=0.15, hi=30.0)
+    g2 = cq.Basis.from_molecule(w2.mol)
+    P2 = P2.copy()
+    P2[0, 3] = np.inf
+    g2.fock2e_2c(_dev(torch, P2))
+    assert g2.sync_status() == cq.CQ_ENONFINITE
+
+
+# ------------------------------------------------------------------ determinism
+def test_deterministic_builds_bitwise_equal(torch_cuda):
+    """Builds give bitwise equal J and K on repeat, with the classes
+    concurrent or serialized, and match the oracle."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, P = case_real(5, inputs.SHELLS_3S2P1D, seed=8, lo=0.1, hi=1.0e3, nocc=10)
+    gb = cq.Basis.from_molecule(w.mol)
+    rng = np.random.default_rng(2)
+    A = inputs.random_symmetric(gb.nbf, rng, -1)
+    runs = [_jk(torch, gb, [P, A], sym=[1, -1], want_j=[True, False]) for _ in range(3)]
+    gb.profile(True, reset=True)
+    runs.append(_jk(torch, gb, [P, A], sym=[1, -1], want_j=[True, False]))
+    gb.profile(False)
+    J0, K0 = runs[0]
+    for J, K in runs[1:]:
+        assert np.array_equal(J[0], J0[0])
+        assert np.array_equal(K[0], K0[0]) and np.array_equal(K[1], K0[1])
+    Jr, Kr = ob.jk(np.stack([P, A]))
+    assert rel_err(J0[0], Jr[0]) < TOL_JK
+    assert rel_err(K0[0], Kr[0]) < TOL_JK and rel_err(K0[1], Kr[1]) < TOL_JK
+    # two-component path
+    w2, ob2, P2 = case_2c(3, inputs.SHELLS_3S2P1D, seed=4, lo=0.3, hi=50.0)
+    g2 = cq.Basis.from_molecule(w2.mol)
+    Gs = [g2.fock2e_2c(_dev(torch, P2)).cpu().numpy() for _ in range(2)]
+    assert np.array_equal(Gs[0], Gs[1])
+    Gr, _ = twocomp.fock2e(ob2, P2)
+    assert rel_err(Gs[0], Gr) < TOL_JK
+
+
+# ------------------------------------------------------------------ screening
+def _host_bounds(gb, ob, P, cnorm):
+    """Quartet bounds exactly as the build forms them: raw Schwarz factors
+    (normalized ones divided by the largest component factors) times the
+    largest |component-scaled X| over the six shell blocks."""
+    o = ob.offsets
+    ns = gb.nshell
+    Q = gb.schwarz().cpu().numpy()
+    Xs = P * np.outer(cnorm, cnorm)
+    Pm = np.zeros((ns, ns))
+    cmax = np.array([cnorm[o[s]:o[s + 1]].max() for s in range(ns)])
+    for a in range(ns):
+        for b in range(ns):
+            Pm[a, b] = np.abs(Xs[o[a]:o[a + 1], o[b]:o[b + 1]]).max()
+    return Q, Pm, cmax
+
+
+def test_screening_elementwise_bound(torch_cuda):
+    """skip > 0 removes quartets with Q_ab Q_cd max|X| < skip.  For every
+    element, the change of J and K must stay within the sum over the removed
+    terms of their bounds (the number of removed (l, s) pairs times each
+    quartet's bound), and the skip counter must equal the host's count."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, P = case_real(12, inputs.SHELLS_2S1P, seed=3, lo=0.15, hi=30.0)
+    gb = cq.Basis.from_molecule(w.mol)
+    _, cnorm = ob.normalized_coefs()
+    assert np.allclose(cnorm, 1.0)   # s and p shells: raw = normalized components
+    tau = 1e-9
+    J0, K0 = _jk(torch, gb, [P])
+    J1, K1 = _jk(torch, gb, [P], th=cq.thresholds(skip=tau))
+    st = gb.build_stats()
+    Q, Pm, _ = _host_bounds(gb, ob, P, cnorm)
+    ns = gb.nshell
+    nf = np.array([ob.nfunc(s) for s in range(ns)])
+    # bound of the quartet {(a,b),(c,d)}: Q_ab Q_cd max of the six blocks
+    a, b, c, d = np.meshgrid(*[np.arange(ns)] * 4, indexing="ij")
+    six = np.maximum.reduce([Pm[a, b], Pm[c, d], Pm[a, c], Pm[a, d], Pm[b, c], Pm[b, d]])
+    bnd = Q[a, b] * Q[c, d] * six
+    skipped = bnd < tau * (1 + 1e-9)
+    # J_mu nu (mu in a, nu in b) loses terms (mu nu|l s) X_ls, l in c, s in d
+    dJ = (skipped * bnd * (nf[c] * nf[d])).sum(axis=(2, 3))
+    # K_mu nu (mu in a, nu in c) loses terms (mu l|nu s) X_ls, l in b, s in d
+    dK = (skipped * bnd * (nf[b] * nf[d])).sum(axis=(1, 3))
+    o = ob.offsets
+    for s1 in range(ns):
+        for s2 in range(ns):
+            blk = (slice(o[s1], o[s1 + 1]), slice(o[s2], o[s2 + 1]))
+            assert np.abs(J1[0][blk] - J0[0][blk]).max() <= dJ[s1, s2] * (1 + 1e-6) + 1e-14
+            assert np.abs(K1[0][blk] - K0[0][blk]).max() <= dK[s1, s2] * (1 + 1e-6) + 1e-14
+    # unique quartets: pairs a >= b (by shell index within equal l ordering
+    # does not matter for a count), bra pair >= ket pair
+    iu = np.array([(x, y) for x in range(ns) for y in range(x + 1)])
+    pa, pb = iu[:, 0], iu[:, 1]
+    qb = Q[pa, pb]
+    n_skip = 0
+    for i in range(len(iu)):
+        x, y = pa[i], pb[i]
+        cc, dd = pa[: i + 1], pb[: i + 1]
+        six = np.maximum.reduce([np.full(i + 1, Pm[x, y]), Pm[cc, dd], Pm[x, cc], Pm[x, dd], Pm[y, cc], Pm[y, dd]])
+        n_skip += int((qb[i] * qb[: i + 1] * six < tau).sum())
+    print(f"skipped {st['skipped']} of {st['skipped'] + st['fp64']} (host {n_skip}); "
+          f"max|dJ| {np.abs(J1[0] - J0[0]).max():.2e}, max|dK| {np.abs(K1[0] - K0[0]).max():.2e}", flush=True)
+    assert st["skipped"] > 0
+    assert abs(st["skipped"] - n_skip) <= max(2, n_skip // 100000)
+
+
+# ------------------------------------------------------------------ C3 recipe
+def test_mixed_recipe_small_full_oracle(torch_cuda):
+    """The mixed-precision recipe at the smallest size (of 6, 8, 10 atoms;
+    2 orbitals per atom) where the configured thresholds route some batches
+    to FP32, every element: FP64 at 1e-10; routed at skip 1e-11 / FP32 below
+    1e-5 within 1e-6 Eh of the oracle."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    th = cq.thresholds(skip=1e-11, mode=1, fp32_below=1e-5)
+    for natom in (6, 8, 10):
+        w, ob, P = case_real(natom, inputs.SHELLS_3S2P1D, seed=0, nocc=2 * natom)
+        gb = cq.Basis.from_molecule(w.mol)
+        J, K = _jk(torch, gb, [P], th=th)
+        st = gb.build_stats()
+        print(f"{natom} atoms (nbf {gb.nbf}) routed: {st}", flush=True)
+        if st["fp32"] > 0:
+            break
+    assert st["fp32"] > 0 and st["fp64"] > 0
+    Jr, Kr = ob.jk(P)
+    E = _energy(P, Jr, Kr)
+    J64, K64 = _jk(torch, gb, [P])
+    assert rel_err(J64[0], Jr) < TOL_JK and rel_err(K64[0], Kr) < TOL_JK
+    dE = abs(_energy(P, J[0], K[0]) - E)
+    print(f"{natom}-atom routed: dE {dE:.2e}, max|dJ| {np.abs(J[0] - Jr).max():.2e}, "
+          f"max|dK| {np.abs(K[0] - Kr).max():.2e}", flush=True)
+    assert dE < 1e-6
+
+
+def test_mixed_recipe_60_atoms_sampled_blocks(torch_cuda):
+    """60 atoms of the mixed-precision recipe (nbf 900, 120 orbitals): FP64
+    without screening on sampled oracle blocks at 1e-10; routed at the
+    configured thresholds within 1e-6 of the same blocks and 1e-6 Eh of the
+    FP64 energy."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.c3(natom=60, nocc=120)
+    ob = oracle.Basis.from_molecule(w.mol)
+    P = oracle.density_real(ob.overlap(), w.orbitals)
+    gb = cq.Basis.from_molecule(w.mol)
+    assert gb.nbf == 900
+    J, K = _jk(torch, gb, [P])
+    Jq, Kq = _jk(torch, gb, [P], th=cq.thresholds(skip=1e-11, mode=1, fp32_below=1e-5))
+    st = gb.build_stats()
+    o = ob.offsets
+    ls = w.mol.shell_l
+    d = np.where(ls == 2)[0]
+    p = np.where(ls == 1)[0]
+    s = np.where(ls == 0)[0]
+    worst = 0.0
+    for a, b in [(int(d[5]), int(p[40])), (int(s[100]), int(d[33]))]:
+        ref = ob.j_block(a, b, P)[0]
+        blk = (slice(o[a], o[a + 1]), slice(o[b], o[b + 1]))
+        assert rel_err(J[0][blk], ref) < TOL_JK, (a, b)
+        worst = max(worst, np.abs(Jq[0][blk] - ref).max())
+    for a, c in [(int(d[12]), int(d[47])), (int(p[7]), int(s[150]))]:
+        ref = ob.k_block(a, c, P)[0]
+        blk = (slice(o[a], o[a + 1]), slice(o[c], o[c + 1]))
+        assert rel_err(K[0][blk], ref) < TOL_JK, (a, c)
+        worst = max(worst, np.abs(Kq[0][blk] - ref).max())
+    dE = abs(_energy(P, Jq[0], Kq[0]) - _energy(P, J[0], K[0]))
+    print(f"60-atom routed: {st}; sampled blocks max|d| vs oracle {worst:.2e}; dE vs FP64 {dE:.2e}; "
+          f"max|dJ| {np.abs(Jq[0] - J[0]).max():.2e} max|dK| {np.abs(Kq[0] - K[0]).max():.2e}", flush=True)
+    assert st["fp32"] > 0 and st["skipped"] > 0
+    assert worst < 1e-6
+    assert dE < 1e-6
+
+
+# ------------------------------------------------------------------ RT recipes
+def _kick(X, Dz, Po, kappa):
+    U = rt.expm_herm(X @ Dz @ X, kappa)
+    return U @ Po @ U.conj().T
+
+
+def test_rt_recipe_em2_step_against_oracle(torch_cuda):
+    """4 atoms of nuclear charge 1 with 3s2p1d shells (exponents 0.1..1e3),
+    2 doubly occupied orbitals: oracle RHF ground state, kick 1e-3 along z,
+    one EM2 step on the GPU against the oracle's EM2 step."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.c5(natom=4)
+    ob = oracle.Basis.from_molecule(w.mol)
+    P, h, S, X, E = scf.rhf(ob, w.mol, 2)
+    Sh = S @ X
+    Po = (Sh @ P @ Sh).astype(complex)
+    Dz = ob.one_electron("dipole", direction=2)
+    P0 = _kick(X, Dz, Po, 1e-3)
+    gb = cq.Basis.from_molecule(w.mol)
+    r = cq.RT(gb, _dev(torch, h), _dev(torch, X), _dev(torch, Dz), _dev(torch, P0), 0.05, cq.RT_EM2)
+    _, mu, nb = r.step(1)
+    Pg = r.density().cpu().numpy()
+    Pref = rt.em2_step(ob, h, X, P0, 0.05)
+    assert list(nb) == [2]
+    assert np.abs(Pg - Pref).max() < 1e-10 * np.abs(Pref).max()
+    _, mu_ref = rt.energy_dipole(ob, h, X, Dz, Pref)
+    assert abs(mu[0] - mu_ref) < 1e-9
+
+
+def test_midpoint_corrector_against_oracle(torch_cuda):
+    """The self-consistent midpoint mode (three EM2 seed steps, then
+    midpoint steps) against the oracle's EM2 and midpoint steps."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.c1()
+    ob = oracle.Basis.from_molecule(w.mol)
+    P, h, S, X, E = scf.rhf(ob, w.mol, 3)
+    Sh = S @ X
+    Po = (Sh @ P @ Sh).astype(complex)
+    Dz = ob.one_electron("dipole", direction=2)
+    P0 = _kick(X, Dz, Po, 1e-2)
+    gb = cq.Basis.from_molecule(w.mol)
+    r = cq.RT(gb, _dev(torch, h), _dev(torch, X), _dev(torch, Dz), _dev(torch, P0), 0.05, cq.RT_MIDPOINT)
+    r.set_params(sc_tol=1e-13, max_iter=80)
+    _, mu, nb = r.step(6)
+    Pg = r.density().cpu().numpy()
+    Pref = P0
+    for k in range(6):
+        if k < 3:
+            Pref = rt.em2_step(ob, h, X, Pref, 0.05)
+        else:
+            Pref, _, _ = rt.midpoint_step(ob, h, X, Pref, 0.05, tol=1e-13)
+    print(f"midpoint builds per step {list(nb)}", flush=True)
+    assert list(nb[:3]) == [2, 2, 2] and min(nb[3:]) >= 2
+    assert np.abs(Pg - Pref).max() < 1e-10 * np.abs(Pref).max()
+    _, mu_ref = rt.energy_dipole(ob, h, X, Dz, Pref)
+    assert abs(mu[-1] - mu_ref) < 1e-9
+
+
+# ------------------------------------------------------------------ general densities
+def test_general_transition_densities(torch_cuda):
+    """Densities with no symmetry (sym = 0), such as the transition
+    densities X = C_occ Y C_vir^T of response sigma-vectors, next to a
+    symmetric and an antisymmetric one: every J and K against the oracle's
+    plain definition at 1e-10, and the identities J[X^T] = J[X],
+    K[X^T] = K[X]^T."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, P = case_real(3, inputs.SHELLS_3S2P1D, seed=11, lo=0.3, hi=50.0)
+    gb = cq.Basis.from_molecule(w.mol)
+    n = gb.nbf
+    rng = np.random.default_rng(31)
+    S = ob.overlap()
+    C = oracle.inv_sqrt(S) @ inputs.random_orbitals(n, n, rng)
+    Y = rng.standard_normal((4, n - 4))
+    T = C[:, :4] @ Y @ C[:, 4:].T           # occupied -> virtual transition density
+    G = rng.standard_normal((n, n))
+    A = inputs.random_symmetric(n, rng, -1)
+    mats = [T, P, G, A, T.T.copy()]
+    sym = [0, 1, 0, -1, 0]
+    J, K = _jk(torch, gb, mats, sym=sym, want_j=[True, True, True, False, True])
+    Jr, Kr = ob.jk_full(np.stack(mats))
+    for m in range(5):
+        if sym[m] != -1:
+            assert rel_err(J[m], Jr[m]) < TOL_JK, m
+        assert rel_err(K[m], Kr[m]) < TOL_JK, m
+    assert np.abs(J[4] - J[0]).max() < 1e-13 * np.abs(J[0]).max()
+    assert np.abs(K[4] - K[0].T).max() < 1e-13 * np.abs(K[0]).max()
+    # 2 + 1 + 2 + 1 + 2 internal slots; eight general densities need 16
+    assert len(_jk(torch, gb, [G] * 8, sym=[0] * 8, want_j=False)[1]) == 8
+    with pytest.raises(cq.CqError):
+        gb.jk([_dev(torch, G)] * 9, sym=[0] * 9)

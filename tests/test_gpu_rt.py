@@ -51,6 +51,21 @@ def c1_state(torch_cuda):
     return w, ob, gb, h, X, Dz, Po
 
 
+def test_zgemm_against_numpy(torch_cuda):
+    """The matrix-core complex GEMM of the real-time path, A B and A B^H,
+    on ragged sizes (tiles of 32, K chunks of 16) against numpy."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    rng = np.random.default_rng(9)
+    for n in (1, 5, 16, 31, 33, 100, 257):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        for conj in (False, True):
+            C = cq.zgemm(_d(torch, A), _d(torch, B), conj).cpu().numpy()
+            ref = A @ (B.conj().T if conj else B)
+            assert np.abs(C - ref).max() < 1e-13 * n * np.abs(A).max() * np.abs(B).max(), (n, conj)
+
+
 def test_expm_against_eigendecomposition(torch_cuda):
     torch = torch_cuda
     from paper_1905_01381_amd import cq
@@ -124,6 +139,26 @@ def test_second_order_in_dt(c1_state, torch_cuda):
         r.close()
     ratio = np.abs(out[0] - out[2]).max() / np.abs(out[1] - out[2]).max()
     assert 4.0 < ratio < 6.0, ratio
+
+
+def test_mmut_against_oracle(c1_state, torch_cuda):
+    """MMUT (the paper's default leap-frog integrator) with EM2 seed and
+    restart every 4 steps against the oracle's MMUT trajectory: step types,
+    densities at 1e-10 after 9 steps, and the dipole."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, gb, h, X, Dz, Po = c1_state
+    P0 = _kick(X, Dz, Po, 1e-2)
+    r = cq.RT(gb, _d(torch, h), _d(torch, X), _d(torch, Dz), _d(torch, P0), 0.05, cq.RT_MMUT)
+    r.set_restart(4)
+    _, mu, nb = r.step(9)
+    Pg = r.density().cpu().numpy()
+    Ps, nb_ref = rt.mmut_trajectory(ob, h, X, P0, 0.05, 9, restart=4)
+    assert list(nb) == nb_ref == [2, 1, 1, 1, 2, 1, 1, 1, 2]
+    assert np.abs(Pg - Ps[-1]).max() < 1e-10 * np.abs(Ps[-1]).max()
+    _, mu_ref = rt.energy_dipole(ob, h, X, Dz, Ps[-1])
+    assert abs(mu[-1] - mu_ref) < 1e-9
+    assert abs(np.trace(Pg).real - 3.0) < 1e-10
 
 
 def test_mlp_kernels_against_oracle(torch_cuda):
