@@ -181,6 +181,31 @@ cq_status cq_jk_build(cq_basis b, int nmat, const double* const* P, const int* s
                       double* const* J, double* const* K, const cq_thresholds* th,
                       hipStream_t stream);
 
+/* cq_jk_build for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as cq_jk_build (results are bitwise
+ * equal to it in the default deterministic mode), except:
+ * - All scratch (packed densities, partial sums, block maxima, counters and
+ *   the stage regions of the high angular momentum classes) comes from one
+ *   static device array of 512 MiB that every GPU the library runs on holds
+ *   until the process ends.  No hipMalloc, hipFree or allocating library
+ *   routine is called.  The basis handle (created beforehand) and the
+ *   caller's P, J, K are used as they are.
+ * - The scratch must hold the densities and partial sums, about
+ *   nel * 8 * (nmat + 2 (nJ + nK)) bytes for nel = sum of nbf_m^2 (e.g. nbf 600
+ *   with 8 densities, 1 J and 8 K: 75 MB), plus one stage region of the largest
+ *   angular momentum class present (1.8 MB for (dd|dd)); larger builds return
+ *   CQ_ENOMEM before any work is enqueued.  The rest of the array holds stage
+ *   regions, which caps the grid of those classes.
+ * - The classes run one after another on `stream` (no internal streams or
+ *   events).
+ * - Every call on a GPU shares that GPU's array and leaves its contents
+ *   behind; each call clears what it needs.  Calls that overlap in time on
+ *   one GPU (other streams, other threads) race and must not be issued. */
+cq_status cq_jk_build_noalloc(cq_basis b, int nmat, const double* const* P, const int* sym,
+                              double* const* J, double* const* K, const cq_thresholds* th,
+                              hipStream_t stream);
+
 /* Two-electron part of the two-component (generalized spin) Fock matrix
  * (paper: Eq. pauli_sep and Eq. 2c_fock, with G^0 = 2 J[P^0] - K[P^0] and
  * G^k = -K[P^k]; the factor 2 follows from the 1/2 in Eq. pauli_sep):

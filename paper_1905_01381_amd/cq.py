@@ -60,6 +60,7 @@ def lib():
         L.cq_schwarz.argtypes = [vp, vp, vp]
         L.cq_jk_build.argtypes = [vp, i, ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(Thresholds), vp]
+        L.cq_jk_build_noalloc.argtypes = L.cq_jk_build.argtypes
         L.cq_fock2e_2c.argtypes = [vp, vp, vp, ctypes.POINTER(Thresholds), vp]
         L.cq_boys.argtypes = [i, i, vp, vp, i, vp]
         L.cq_sync_status.argtypes = [vp, vp]
@@ -95,7 +96,7 @@ def lib():
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
                      "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
-                     "cq_mlp_eval", "cq_mlp_adam", "cq_sync_status", "cq_jk_size_check", "cq_rt_set_restart", "cq_zgemm"):
+                     "cq_mlp_eval", "cq_mlp_adam", "cq_sync_status", "cq_jk_size_check", "cq_jk_build_noalloc", "cq_rt_set_restart", "cq_zgemm"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -244,9 +245,11 @@ class Basis:
         _check(lib().cq_schwarz(self.h, _ptr(Q), _stream(stream)))
         return Q
 
-    def jk(self, P, sym=None, want_j=True, want_k=True, th: Thresholds | None = None, out=None, stream=None):
+    def jk(self, P, sym=None, want_j=True, want_k=True, th: Thresholds | None = None, out=None, stream=None,
+           noalloc: bool = False):
         """J[X_m], K[X_m] for a list of densities (device float64 [nbf, nbf]).
-        ``want_j`` / ``want_k``: bool or per-density list of bools."""
+        ``want_j`` / ``want_k``: bool or per-density list of bools.
+        ``noalloc``: cq_jk_build_noalloc (static scratch, no device allocation)."""
         import torch
         Ps = list(P) if isinstance(P, (list, tuple)) else [P]
         n = len(Ps)
@@ -266,7 +269,8 @@ class Basis:
         pK = arr(*[(k.data_ptr() if k is not None else 0) for k in K])
         psym = (ctypes.c_int * n)(*sym)
         thp = ctypes.byref(th) if th is not None else None
-        _check(lib().cq_jk_build(self.h, n, pP, psym, pJ, pK, thp, _stream(stream)))
+        fn = lib().cq_jk_build_noalloc if noalloc else lib().cq_jk_build
+        _check(fn(self.h, n, pP, psym, pJ, pK, thp, _stream(stream)))
         return JKResult(J, K)
 
     def fock2e_2c(self, P2c, th: Thresholds | None = None, out=None, stream=None):
