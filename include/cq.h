@@ -21,6 +21,9 @@
  * - Functions are ordered shell by shell in the order given to
  *   cq_basis_create; within a shell, Cartesian components are lexicographic
  *   (l=1: x y z; l=2: xx xy xz yy yz zz), each normalized to unit self-overlap.
+ *   Bases made by cq_basis_create_general may also hold spherical d shells
+ *   and generally contracted shells (see there); nbf then counts the
+ *   caller's functions.
  * - Work is enqueued on the given stream (NULL = the default stream) and is
  *   asynchronous unless stated.  A handle must not be used from two streams
  *   at the same time.
@@ -119,6 +122,34 @@ cq_status cq_basis_create_batch(int nmol, const int* nshell_mol, const double* x
                                 const int* nprim, const double* alpha, const double* coef,
                                 hipStream_t stream, cq_basis* out);
 
+/* A basis of segmented or generally contracted shells, each Cartesian or
+ * spherical (paper: Introduction, contracted Gaussian basis functions with
+ * general or segmented contraction).  Arguments as in
+ * cq_basis_create_batch (nmol = 1 for one molecule), plus, per shell:
+ *   ncontr[nshell]  host, contractions over the shell's nprim exponents
+ *                   (1 = segmented, up to 64)
+ *   pure[nshell]    host, 1 = spherical, 0 = Cartesian; for l <= 1 the two
+ *                   are the same (p stays x, y, z)
+ *   coef[]          per shell ncontr rows of nprim raw coefficients
+ *                   (contraction-major), shells one after another
+ *                   (sum nprim * ncontr entries; alpha has sum nprim)
+ * A shell with ncontr contractions contributes its functions contraction by
+ * contraction: contraction k is the segmented shell with coefficient row k,
+ * normalized as in cq_basis_create.  A spherical d shell has 5 functions,
+ * the unit-normalized real solid harmonics m = -2..2: xy, yz,
+ * (3z^2 - r^2), xz, (x^2 - y^2) (each as a combination of the normalized
+ * Cartesian xx..zz of the same contraction).  Every matrix of the handle
+ * (densities, J, K, one-electron integrals, cq_fock2e_2c's spin blocks, the
+ * real-time matrices) is in these functions; internally the integrals run
+ * over Cartesian segmented shells and densities pass through the d-shell
+ * transformation on the way in, results on the way out.  Shell-level
+ * outputs (cq_schwarz, cq_eri_quartet, cq_basis_nshell) refer to the
+ * expanded Cartesian segmented shells.  l = 3 and above: CQ_EUNSUPPORTED.
+ * Allocates and synchronizes like cq_basis_create. */
+cq_status cq_basis_create_general(int nmol, const int* nshell_mol, const double* xyz, const int* l,
+                                  const int* nprim, const int* ncontr, const int* pure, const double* alpha,
+                                  const double* coef, hipStream_t stream, cq_basis* out);
+
 /* Molecules in a handle (1 for cq_basis_create; -1 on NULL) and the basis
  * functions of each, written to HOST nbf_mol[nmol]. */
 int cq_basis_nmol(cq_basis b);
@@ -127,7 +158,8 @@ cq_status cq_basis_mol_nbf(cq_basis b, int* nbf_mol);
 /* Release a basis and all of its device memory (synchronizes the device). */
 cq_status cq_basis_destroy(cq_basis b);
 
-/* Number of basis functions / shells of a basis (-1 on a NULL handle). */
+/* Number of basis functions (the caller's) / shells (after expanding
+ * general contractions) of a basis (-1 on a NULL handle). */
 int cq_basis_nbf(cq_basis b);
 int cq_basis_nshell(cq_basis b);
 
@@ -194,7 +226,7 @@ cq_status cq_jk_build(cq_basis b, int nmat, const double* const* P, const int* s
  * - The scratch must hold the densities and partial sums, about
  *   nel * 8 * (nmat + 2 (nJ + nK)) bytes for nel = sum of nbf_m^2 (e.g. nbf 600
  *   with 8 densities, 1 J and 8 K: 75 MB), plus one stage region of the largest
- *   angular momentum class present (1.8 MB for (dd|dd)); larger builds return
+ *   angular momentum class present (1.7 MB for (dd|dd)); larger builds return
  *   CQ_ENOMEM before any work is enqueued.  The rest of the array holds stage
  *   regions, which caps the grid of those classes.
  * - The classes run one after another on `stream` (no internal streams or
@@ -244,24 +276,41 @@ cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, in
 cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t stream);
 
 /* Autotuner for the electron-repulsion launches of this handle: for every
- * class it times candidate orientations (as generated, and with bra and ket
- * exchanged where that kernel exists), task shapes (length of the c range
- * one wave walks: the default, half, twice and four times it, at most 64) and
- * grid caps (one wave per task, or 2048 waves looping over tasks) with HIP
- * events, each `reps` times (1..100), on a synthetic density of nmat slots,
- * and keeps the fastest for every later build on the handle.  Results do not depend on the
- * choice beyond the order of floating-point atomic additions.  Synchronizes
- * `stream`; overwrites the handle's work buffers only. */
+ * class it times, with HIP events, each `reps` times (1..100), on a
+ * synthetic density of nmat slots:
+ *   1. orientations (as generated, and with bra and ket exchanged where
+ *      that kernel exists) x task shapes (length of the c range one wave
+ *      walks: the default, half, twice and four times it, at most 64) x grid
+ *      caps (one wave per task, or 2048 waves looping over tasks);
+ *   2. at the fastest of those, the walk rotation (tasks start their c walk
+ *      at step task mod length, spreading the flushes of tasks that share a
+ *      bra shell) and every LDS accumulator level below the highest that
+ *      fits (less LDS per wave, more resident waves, more flushes);
+ * and keeps the fastest for every later build on the handle.  Every plan is
+ * deterministic; two plans agree to rounding only (the FP64 partial sums a
+ * wave forms before its exact fixed-point additions depend on the plan).
+ * Synchronizes `stream`; overwrites the handle's work buffers only. */
 cq_status cq_autotune(cq_basis b, int nmat, int reps, hipStream_t stream);
 
-/* The launch plan per class (tuned or default): for k < cap,
- * rec[8k..8k+7] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks,
- * exchanged) and ms[k] = best time measured by cq_autotune (0 if not tuned);
- * *n = classes with work.  exchanged = 1: the class runs with bra and ket
- * pairs exchanged, (lc ld|la lb), which loops over the other pair's first
- * shell and flushes fewer exchange partial sums per step (built for (pp|ps),
- * (dp|ps), (dp|ds) and (dd|ps); the default there).  Host arrays. */
+/* The launch plan per class (tuned, set or default): for k < cap,
+ * rec[10k..10k+9] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks,
+ * exchanged, LDS level or -1, rotation) and ms[k] = best time measured by
+ * cq_autotune (0 if not tuned); *n = classes with work.  exchanged = 1: the
+ * class runs with bra and ket pairs exchanged, (lc ld|la lb), which loops
+ * over the other pair's first shell and flushes fewer exchange partial sums
+ * per step (built for (pp|ps), (dp|ps), (dp|ds) and (dd|ps)).  LDS level -1:
+ * the highest that fits for the build's density count (0: none, 1: J'_ab and
+ * K'_ad, 2: also K'_bd).  Host arrays. */
 cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
+
+/* Set the launch plan of n classes from records laid out as
+ * cq_autotune_read writes them (the tasks field is ignored), e.g. a plan
+ * tuned earlier on the same molecules.  Every record is checked first
+ * (class with work on this basis, c-range length 1..64, grid cap >= 0,
+ * exchanged 0/1 and built, LDS level -1..2, rotation 0/1; CQ_EINVAL
+ * otherwise, nothing changed).  Re-uploads the classes' task lists
+ * (allocates); not stream-ordered: no build may be in flight on the handle. */
+cq_status cq_plan_set(cq_basis b, int n, const int* rec);
 
 /* Per-class launch timing with HIP events recorded on the launch stream
  * (tracing aid).  enable: 0 off, 1 on, 2 on and reset the totals.  Builds
@@ -272,6 +321,12 @@ cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
  * that ran, cls[4k..4k+3], the summed kernel time ms[k] and launch count
  * count[k]; *n = number of such classes. */
 cq_status cq_profile(cq_basis b, int enable);
+
+/* Progress trace (tracing aid): with enable != 0, every build on this handle
+ * prints "[cq] class (ab|cd) done" to stderr as each class's kernels finish
+ * (a host function enqueued on the launch stream after them).  Off by
+ * default; adds one host callback per class and build. */
+cq_status cq_trace(cq_basis b, int enable);
 cq_status cq_profile_read(cq_basis b, int maxn, int* cls, double* ms, long long* count, int* n);
 
 /* ---- real-time propagation (paper: "Real-Time Electronic Dynamics") ---- */

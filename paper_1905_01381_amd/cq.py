@@ -47,11 +47,13 @@ def lib():
         L.cq_last_error.restype = ctypes.c_char_p
         L.cq_basis_create.argtypes = [i, dp, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
         L.cq_basis_create_batch.argtypes = [i, ip, dp, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
+        L.cq_basis_create_general.argtypes = [i, ip, dp, ip, ip, ip, ip, dp, dp, vp, ctypes.POINTER(vp)]
         L.cq_basis_nmol.argtypes = [vp]
         L.cq_basis_nmol.restype = i
         L.cq_basis_mol_nbf.argtypes = [vp, ip]
         L.cq_autotune.argtypes = [vp, i, i, vp]
         L.cq_autotune_read.argtypes = [vp, i, ip, ctypes.POINTER(ctypes.c_float), ip]
+        L.cq_plan_set.argtypes = [vp, i, ip]
         L.cq_basis_destroy.argtypes = [vp]
         L.cq_basis_nbf.argtypes = [vp]
         L.cq_basis_nbf.restype = i
@@ -70,6 +72,7 @@ def lib():
         llp = ctypes.POINTER(ctypes.c_longlong)
         L.cq_quartet_counts.argtypes = [vp, i, ip, llp, ip]
         L.cq_profile.argtypes = [vp, i]
+        L.cq_trace.argtypes = [vp, i]
         L.cq_build_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong), vp]
         fp = ctypes.POINTER(ctypes.c_float)
         L.cq_rt_create.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, i, vp, ctypes.POINTER(vp)]
@@ -90,9 +93,10 @@ def lib():
         L.cq_mlp_eval.argtypes = [vp, vp, vp, i, vp, vp, vp]
         L.cq_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, i, vp]
         L.cq_profile_read.argtypes = [vp, i, ip, dp, llp, ip]
-        for name in ("cq_basis_create", "cq_basis_create_batch", "cq_basis_mol_nbf", "cq_autotune",
+        for name in ("cq_basis_create", "cq_basis_create_batch", "cq_basis_create_general", "cq_basis_mol_nbf",
+                     "cq_autotune", "cq_plan_set",
                      "cq_autotune_read", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
-                     "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile",
+                     "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile", "cq_trace",
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
                      "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
@@ -152,7 +156,11 @@ class Basis:
     batch: its matrices are flat tensors of the concatenated per-molecule
     [nbf_m, nbf_m] blocks (see ``pack`` / ``unpack``)."""
 
-    def __init__(self, shell_xyz, shell_l, nprim, alpha, coef, stream=None, nshell_mol=None):
+    def __init__(self, shell_xyz, shell_l, nprim, alpha, coef, stream=None, nshell_mol=None, ncontr=None,
+                 pure=None):
+        """``ncontr`` / ``pure`` (per shell) select cq_basis_create_general:
+        generally contracted shells (``coef`` then holds ncontr rows of nprim
+        per shell) and spherical d shells."""
         xyz = np.ascontiguousarray(shell_xyz, dtype=np.float64).reshape(-1)
         l = np.ascontiguousarray(shell_l, dtype=np.int32)
         npr = np.ascontiguousarray(nprim, dtype=np.int32)
@@ -160,7 +168,18 @@ class Basis:
         c = np.ascontiguousarray(coef, dtype=np.float64)
         h = ctypes.c_void_p()
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
-        if nshell_mol is None:
+        if ncontr is not None or pure is not None:
+            nco = np.ascontiguousarray(np.ones(l.size) if ncontr is None else ncontr, dtype=np.int32)
+            pu = np.ascontiguousarray(np.zeros(l.size) if pure is None else pure, dtype=np.int32)
+            nsm = np.ascontiguousarray([l.size] if nshell_mol is None else nshell_mol, dtype=np.int32)
+            if nco.size != l.size or pu.size != l.size or int(nsm.sum()) != l.size:
+                raise ValueError("ncontr, pure and nshell_mol must match the shells")
+            _check(lib().cq_basis_create_general(int(nsm.size), nsm.ctypes.data_as(ip), xyz.ctypes.data_as(dp),
+                                                 l.ctypes.data_as(ip), npr.ctypes.data_as(ip),
+                                                 nco.ctypes.data_as(ip), pu.ctypes.data_as(ip),
+                                                 a.ctypes.data_as(dp), c.ctypes.data_as(dp), _stream(stream),
+                                                 ctypes.byref(h)))
+        elif nshell_mol is None:
             _check(lib().cq_basis_create(int(l.size), xyz.ctypes.data_as(dp), l.ctypes.data_as(ip),
                                          npr.ctypes.data_as(ip), a.ctypes.data_as(dp), c.ctypes.data_as(dp),
                                          _stream(stream), ctypes.byref(h)))
@@ -175,7 +194,8 @@ class Basis:
         self.h = h
         self.nbf = lib().cq_basis_nbf(h)
         self.nshell = lib().cq_basis_nshell(h)
-        self.shell_l = l.copy()
+        # shells as the library holds them: general contractions expanded
+        self.shell_l = np.repeat(l, np.asarray(ncontr, dtype=np.int64)) if ncontr is not None else l.copy()
         self.nmol = lib().cq_basis_nmol(h)
         nb = np.zeros(self.nmol, np.int32)
         _check(lib().cq_basis_mol_nbf(h, nb.ctypes.data_as(ip)))
@@ -188,15 +208,23 @@ class Basis:
 
     @classmethod
     def from_molecule(cls, mol, stream=None) -> "Basis":
-        return cls(mol.shell_xyz, mol.shell_l, mol.nprim, mol.alpha, mol.coef, stream)
+        return cls(mol.shell_xyz, mol.shell_l, mol.nprim, mol.alpha, mol.coef, stream,
+                   ncontr=getattr(mol, "ncontr", None), pure=getattr(mol, "pure", None))
 
     @classmethod
     def from_molecules(cls, mols, stream=None) -> "Basis":
         """A batch handle over a list of molecules."""
+        general = any(getattr(m, "ncontr", None) is not None or getattr(m, "pure", None) is not None for m in mols)
+        kw = {}
+        if general:
+            kw["ncontr"] = np.concatenate([m.ncontr if getattr(m, "ncontr", None) is not None
+                                           else np.ones(m.nshell, np.int32) for m in mols])
+            kw["pure"] = np.concatenate([m.pure if getattr(m, "pure", None) is not None
+                                         else np.zeros(m.nshell, np.int32) for m in mols])
         return cls(np.concatenate([np.asarray(m.shell_xyz).reshape(-1, 3) for m in mols]),
                    np.concatenate([m.shell_l for m in mols]), np.concatenate([m.nprim for m in mols]),
                    np.concatenate([m.alpha for m in mols]), np.concatenate([m.coef for m in mols]), stream,
-                   nshell_mol=[len(m.shell_l) for m in mols])
+                   nshell_mol=[len(m.shell_l) for m in mols], **kw)
 
     def pack(self, mats):
         """Concatenate per-molecule [nbf_m, nbf_m] device matrices into one flat batch tensor."""
@@ -213,18 +241,29 @@ class Basis:
         return self.plan()
 
     def plan(self) -> list:
-        """The launch plan per class: (la, lb, lc, ld), c-range length, grid cap, tasks, tuned ms."""
+        """The launch plan per class: (la, lb, lc, ld), c-range length, grid
+        cap, tasks, orientation, LDS level (-1: highest that fits), walk
+        rotation, tuned ms."""
         n = ctypes.c_int()
-        rec = np.zeros(8 * 32, np.int32)
+        rec = np.zeros(10 * 32, np.int32)
         ms = np.zeros(32, np.float32)
         _check(lib().cq_autotune_read(self.h, 32, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                       ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
         out = []
         for k in range(min(n.value, 32)):
-            r = rec[8 * k:8 * k + 8]
+            r = rec[10 * k:10 * k + 10]
             out.append({"cls": tuple(int(x) for x in r[:4]), "cl": int(r[4]), "grid": int(r[5]),
-                        "tasks": int(r[6]), "exchanged": int(r[7]), "ms": float(ms[k])})
+                        "tasks": int(r[6]), "exchanged": int(r[7]), "acc": int(r[8]), "rot": int(r[9]),
+                        "ms": float(ms[k])})
         return out
+
+    def set_plan(self, plan: list) -> None:
+        """Apply plan records (as returned by ``plan``) to their classes."""
+        rec = np.zeros(10 * max(len(plan), 1), np.int32)
+        for k, p in enumerate(plan):
+            rec[10 * k:10 * k + 10] = [*p["cls"], p["cl"], p["grid"], p.get("tasks", 0), p.get("exchanged", 0),
+                                       p.get("acc", -1), p.get("rot", 0)]
+        _check(lib().cq_plan_set(self.h, len(plan), rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -322,6 +361,10 @@ class Basis:
 
     def profile(self, enable: bool = True, reset: bool = False):
         _check(lib().cq_profile(self.h, 2 if (enable and reset) else int(enable)))
+
+    def trace(self, enable: bool = True):
+        """Print "[cq] class (ab|cd) done" to stderr as each class of a build finishes."""
+        _check(lib().cq_trace(self.h, int(enable)))
 
     def profile_read(self) -> dict:
         """{(la, lb, lc, ld): (total kernel ms, launches)} from HIP events."""

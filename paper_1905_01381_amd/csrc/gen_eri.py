@@ -436,13 +436,16 @@ STAGE_CFG = {
 # (ps|ss) from 3 to 4, 17 % and 8 % faster on MI355X; (pp|ss) at 3 waves
 # was slower, and classes further from a step spill inside the loop.
 # (ss|ss) and (ds|ps) sit a few registers above 5 and 2 waves with the
-# fixed-point flushes and the LDS task accumulators ((pp|ps) at 2 waves
-# spilled inside the loop and was slower).
+# fixed-point flushes and the LDS task accumulators.  (pp|ps) needs 270
+# registers at one wave; at two it spills 56 bytes per lane, all of it at
+# the task and step level, and went from 58.3 to 47.7 ms per launch on the
+# 40-atom 3s2p1d two-component build.
 UNSTAGED_WAVES = {
     (0, 0, 0, 0): 5,
     (1, 0, 1, 0): 3,
     (1, 0, 0, 0): 4,
     (2, 0, 1, 0): 2,
+    (1, 1, 1, 0): 2,
 }
 
 
@@ -709,6 +712,15 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
         ("K_bd", [(j, l) for j in range(nb) for l in range(nd)], [(i, k) for i in range(na) for k in range(nc)],
          lambda o, s: Vi(s[0], o[0], s[1], o[1]), ("fa", "fc"), ("K", "fb", "fd", "ks"), "none", "active", ""),
     ]
+    # J'_ab, K'_ad and K'_bd do not depend on c: they are summed over the
+    # task's c walk in the wave's own stage region (each entry read and
+    # written by one lane only, so in a fixed order) and added to J'/K' once
+    # per task (emit_staged_acc_flush) instead of every step
+    nb_nd, na_nb = nb * nd, na * nb
+    sacc_entry = {"J_ab": lambda o: nb_nd + o[0] * nb + o[1],
+                  "K_ad": lambda o: nb_nd + na_nb + o[0] * nd + o[1],
+                  "K_bd": lambda o: o[0] * nd + o[1]}
+    sacc_guard = {"J_ab": "dj == 0", "K_ad": "bi == 0", "K_bd": None}
     for (name, outs, sums, vfn, (xr, xc), (arr, dr, dc, slot), rd, guard, scale) in specs:
         isJ = arr == "J"
         # outputs in groups of g: the group's integrals stay in registers and
@@ -735,7 +747,13 @@ def emit_staged_digest(out: Emitter, la, lb, lc, ld):
                 elif rd != "none":
                     val = f"{red(rd)}({val})"
                 out(f"    {{ const {T_()} s = {val};")
-                out(f"      if ({guard}) acc_{arr.lower()}(mc, {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s); }}")
+                if name in sacc_entry and (la, lb, lc, ld) in STAGE_ACC_CLASSES:
+                    e = f"SACC(m, {sacc_entry[name](o)})"
+                    g_ = sacc_guard[name]
+                    upd = f"STS({e}, STL({e}) + (double)s);"
+                    out(f"      {'if (' + g_ + ') ' if g_ else ''}{upd} }}")
+                else:
+                    out(f"      if ({guard}) acc_{arr.lower()}(mc, {idxf}(dg, mc, {dr} + {o[0]}, {dc} + {o[1]}, {slot}), s); }}")
             out("  }")
             out("}")
 
@@ -752,6 +770,55 @@ def all_classes(lmax):
 HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 // Head-Gordon-Pople electron-repulsion kernels (one thread per contracted
 // shell quartet) with Coulomb/exchange digestion."""
+
+
+# Staged classes that sum J'_ab, K'_ad and K'_bd over a task in their stage
+# region.  Measured on the 40-atom 3s2p1d two-component build: (dp|pp)
+# 110.8 -> 82.0 ms and (dp|dp) 84.5 -> 83.1 ms (two waves per SIMD); the
+# one-wave classes, which cannot hide the read-modify-write latency behind
+# another wave, were 3-8 % slower and keep the per-step flush.
+STAGE_ACC_CLASSES = {(2, 1, 1, 1), (2, 1, 2, 1)}
+
+
+def staged_acc_doubles(la, lb, lc, ld):
+    """Stage-region doubles per lane and density slot for the task
+    accumulators of a staged class: K'_bd, J'_ab, K'_ad (in that order)."""
+    if (la, lb, lc, ld) not in STAGE_ACC_CLASSES:
+        return 0
+    na, nb, nd = ncart(la), ncart(lb), ncart(ld)
+    return nb * nd + na * nb + na * nd
+
+
+def emit_staged_acc_zero(o: Emitter, la, lb, lc, ld):
+    o(f"    for (int t = 0; t < {staged_acc_doubles(la, lb, lc, ld)} * dg.nX; ++t) STS(SACC(0, t), 0.0);")
+
+
+def emit_staged_acc_flush(o: Emitter, la, lb, lc, ld):
+    """Once per task: add the stage accumulators to J' and K' (fixed point)."""
+    na, nb, nd = ncart(la), ncart(lb), ncart(ld)
+    o("    stage_fence();")
+    o("    for (int m = 0; m < dg.nX; ++m) {")
+    o("      const int js = dg.jslot[m], ks = dg.kslot[m];")
+    o("      if (js >= 0 && dj == 0 && rowv) {")
+    for i in range(na):
+        for j in range(nb):
+            o(f"        {{ const double s = STL(SACC(m, {nb * nd + i * nb + j}));")
+            o(f"          if (s != 0.0) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
+    o("      }")
+    o("      if (ks >= 0 && bi == 0 && fdv >= 0) {")
+    for i in range(na):
+        for l in range(nd):
+            o(f"        {{ const double s = STL(SACC(m, {nb * nd + na * nb + i * nd + l}));")
+            o(f"          if (s != 0.0) acc_k(mc, kidx(dg, mc, fa + {i}, fdv + {l}, ks), s); }}")
+    o("      }")
+    o("      if (ks >= 0 && rowv && fdv >= 0) {")
+    for j in range(nb):
+        for l in range(nd):
+            o(f"        {{ const double s = STL(SACC(m, {j * nd + l}));")
+            o(f"          if (s != 0.0) acc_k(mc, kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
+    o("      }")
+    o("    }")
+    o("    stage_fence();")
 
 
 def acc_doubles(la, lb, lc, ld):
@@ -857,11 +924,16 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * 8} * dg.nX;")
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
+    sacc = staged_acc_doubles(la, lb, lc, ld)
     if staged:
-        o(f"  const stage_rsrc srs = stage_make(dg.stage + (size_t)blockIdx.x * ({stage_n} * 64), {stage_n} * 512);")
+        # per-wave region: the integral stage, then the task accumulators
+        # ([density slot][entry] per lane)
+        o(f"  const int sreg = {stage_n} + {sacc} * dg.nX;")
+        o(f"  const stage_rsrc srs = stage_make(dg.stage + (size_t)blockIdx.x * ((size_t)sreg * 64), sreg * 512);")
         o("  const int svo = lane * 8;")
         o("#define STL(i) stage_load(srs, svo, (i))")
         o("#define STS(i, x) stage_store(srs, svo, (i), (x))")
+        o(f"#define SACC(m, e) ({stage_n} + (m) * {sacc} + (e))")
     # With screening or routing, the build's classification pass lists the
     # tasks that have steps of this kernel's precision and marks those steps
     # (bit c - c_lo of the task's mask); the kernel walks only them.
@@ -887,9 +959,21 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     o("    const int c_lo = tk.w, c_hi = tk2.w;")
     if kbd:
         emit_acc_zero(o, la, lb, lc, ld)
+    if sacc:
+        emit_staged_acc_zero(o, la, lb, lc, ld)
+    if kbd or sacc:
         o("    int fdv = -1;  // first function of d (valid once a step with this d ran)")
-    o("    for (int c_idx = c_lo; c_idx <= c_hi; ++c_idx) {")
-    o("      if (!((smask >> (c_idx - c_lo)) & 1ull)) continue;")
+    # With dg.rot the walk over the c range starts at step (task mod length)
+    # and wraps around, so that tasks sharing a bra shell a do not flush the
+    # same K'_ac elements at the same time; the steps and their sums are the
+    # same in either order.
+    o("    const int n_st = c_hi - c_lo + 1;")
+    o("    const int rot0 = dg.rot ? task % n_st : 0;")
+    o("    for (int st = 0; st < n_st; ++st) {")
+    o("      int s_i = st + rot0;")
+    o("      if (s_i >= n_st) s_i -= n_st;")
+    o("      if (!((smask >> s_i) & 1ull)) continue;")
+    o("      const int c_idx = c_lo + s_i;")
     o("      const int c = tm.shl_c[c_idx];")
     o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
     o("      bool active = rowv && colv;")
@@ -897,7 +981,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
     o(f"      const int jk = mc.ppos[spair(mc, c, colv ? d : {'c' if same_cd else 'd'})];")
     o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
-    if kbd:
+    if kbd or sacc:
         o("      if (colv) fdv = fd;")
     o("      if (dg.skip > 0.0 && active) active = quartet_bound(mc, bra.Q[ib], ket.Q[jk], a, b, c, d) >= dg.skip;")
     o("      if (!__any(active)) continue;")
@@ -920,10 +1004,13 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     o("    }")
     if kbd:
         emit_acc_flush(o, la, lb, ld)
+    if sacc:
+        emit_staged_acc_flush(o, la, lb, lc, ld)
     o("  }")
     if staged:
         o("#undef STL")
         o("#undef STS")
+        o("#undef SACC")
     o("}")
     o("")
     return o.text(), nvrr, stage_n
@@ -1004,8 +1091,8 @@ def gen(lmax: int) -> dict:
     # dispatch tables
     o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
     o("// jks / jk32s: the kernels of the exchanged orientation (lc ld|la lb), or NULL; acc_s / acc8_s their")
-    o("// LDS accumulator sizes")
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; int acc8; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); eri_jk_fn jks; eri_jk_fn jk32s; int acc_s, acc8_s; };")
+    o("// LDS accumulator sizes; sacc: stage-region task accumulator doubles per lane and density slot")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; int acc8; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); eri_jk_fn jks; eri_jk_fn jk32s; int acc_s, acc8_s; int sacc; };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
@@ -1016,7 +1103,7 @@ def gen(lmax: int) -> dict:
             sw = f"eri_jk_{sn}, eri_jk32_{sn}, {acc_doubles(lc, ld, la, lb)}, {acc8_doubles(lc, ld, la, lb)}"
         else:
             sw = "nullptr, nullptr, 0, 0"
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, {acc8_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}, {sw}}},")
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, {acc8_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}, {sw}, {staged_acc_doubles(la, lb, lc, ld)}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)

@@ -18,6 +18,17 @@ orbitals; ``numpy.random.default_rng(seed)``):
   coefficients are U(0.1, 1), one triple per shell in atom-major order.
 * Orbitals: Q from the QR factorization of a standard-normal matrix (complex
   normal for two-component spinors); callers form C = S^{-1/2} Q.
+* Spherical variant (``spherical=True``): the same draws, with every d shell
+  taken as spherical (5 functions instead of 6): 3s2p1d gives 14 functions
+  per atom.
+* General-contraction variant (``general_molecule``): per atom, the n_l
+  shells of one l become one generally contracted shell with n_l
+  contractions over m = min(3 n_l, 8) geometric exponents from ``hi`` down
+  to ``lo``.  Contraction k weights its own window of primitives
+  [k m / n_l, (k+1) m / n_l) with U(0.1, 1) and every other primitive with
+  U(0, 0.05), so that the contractions share every exponent yet stay far
+  from linearly dependent.  Draw order per atom and shell: geometry first,
+  then the n_l x m coefficients row by row, then the orbitals.
 
 The contracted Gaussian basis itself follows the paper's LCAO setting
 (Introduction: contracted Gaussian-type orbital expansions, segmented
@@ -48,8 +59,10 @@ class Molecule:
     shell_xyz: np.ndarray             # [nshell, 3]
     nprim: np.ndarray                 # [nshell] int
     alpha: np.ndarray                 # [sum nprim]
-    coef: np.ndarray                  # [sum nprim] raw (unnormalized)
+    coef: np.ndarray                  # [sum nprim * ncontr] raw (unnormalized), contraction-major per shell
     rng_state: dict = field(default_factory=dict, repr=False)
+    ncontr: np.ndarray | None = None  # [nshell] contractions per shell (None: all 1)
+    pure: np.ndarray | None = None    # [nshell] 1 = spherical shell (None: all Cartesian)
 
     @property
     def nshell(self) -> int:
@@ -57,7 +70,18 @@ class Molecule:
 
     @property
     def nbf(self) -> int:
-        return int(sum((l + 1) * (l + 2) // 2 for l in self.shell_l))
+        n = 0
+        for s, l in enumerate(self.shell_l):
+            nf = 2 * l + 1 if (self.pure is not None and self.pure[s] and l >= 2) else (l + 1) * (l + 2) // 2
+            n += nf * (1 if self.ncontr is None else int(self.ncontr[s]))
+        return int(n)
+
+    def as_spherical(self) -> "Molecule":
+        """The same shells with every d shell spherical."""
+        pure = (np.asarray(self.shell_l) >= 2).astype(np.int32)
+        nco = self.ncontr if self.ncontr is not None else np.ones(self.nshell, np.int32)
+        return Molecule(self.atoms, self.charges, self.shell_atom, self.shell_l, self.shell_xyz, self.nprim,
+                        self.alpha, self.coef, self.rng_state, nco, pure)
 
 
 def lattice_geometry(natom: int, rng: np.random.Generator) -> np.ndarray:
@@ -107,6 +131,36 @@ def make_molecule(natom: int, ls: list[int], lo: float, hi: float,
     )
 
 
+def general_molecule(natom: int, ls: list[int], lo: float, hi: float, rng: np.random.Generator,
+                     spherical: bool = True, charge: float = 1.0) -> Molecule:
+    """The recipe's atoms with the n_l shells of each l merged into one
+    generally contracted shell (n_l contractions over min(3 n_l, 8)
+    exponents); d shells spherical if ``spherical``."""
+    atoms = lattice_geometry(natom, rng)
+    counts = {l: ls.count(l) for l in sorted(set(ls))}
+    per_atom = []
+    for l, n in counts.items():
+        per_atom.append((l, min(NPRIM * n, 8), n, np.geomspace(hi, lo, min(NPRIM * n, 8))))
+    sh_atom, sh_l, npr, nco, alpha, coef = [], [], [], [], [], []
+    for a in range(natom):
+        for l, npl, nc, ex in per_atom:
+            sh_atom.append(a)
+            sh_l.append(l)
+            npr.append(npl)
+            nco.append(nc)
+            alpha.append(ex)
+            for k in range(nc):
+                own = np.zeros(npl, bool)
+                own[k * npl // nc:(k + 1) * npl // nc] = True
+                coef.append(np.where(own, rng.uniform(0.1, 1.0, npl), rng.uniform(0.0, 0.05, npl)))
+    sh_atom = np.array(sh_atom, np.int32)
+    sh_l = np.array(sh_l, np.int32)
+    return Molecule(atoms=atoms, charges=np.full(natom, charge), shell_atom=sh_atom, shell_l=sh_l,
+                    shell_xyz=atoms[sh_atom].copy(), nprim=np.array(npr, np.int32),
+                    alpha=np.concatenate(alpha), coef=np.concatenate(coef), ncontr=np.array(nco, np.int32),
+                    pure=((sh_l >= 2) & spherical).astype(np.int32))
+
+
 def random_orbitals(nbf: int, nocc: int, rng: np.random.Generator, complex_: bool = False) -> np.ndarray:
     """Orthonormal columns Q (nbf x nocc) from QR of a (complex) normal matrix."""
     if complex_:
@@ -141,11 +195,14 @@ def c1(seed: int = 0) -> Workload:
     return Workload("C1", mol, q, False, 5)
 
 
-def c2(seed: int = 0, natom: int = 40, nocc: int = 60) -> Workload:
-    """40 atoms, 3s2p1d per atom (exponents 0.1..1e3), nbf = 600 Cartesian;
-    60 complex spinors in the 2*nbf spin-blocked space."""
+def c2(seed: int = 0, natom: int = 40, nocc: int = 60, spherical: bool = False) -> Workload:
+    """40 atoms, 3s2p1d per atom (exponents 0.1..1e3), nbf = 600 Cartesian
+    (560 with spherical d); 60 complex spinors in the 2*nbf spin-blocked
+    space."""
     rng = np.random.default_rng(seed)
     mol = make_molecule(natom, SHELLS_3S2P1D, 0.1, 1.0e3, rng)
+    if spherical:
+        mol = mol.as_spherical()
     q = random_orbitals(2 * mol.nbf, nocc, rng, complex_=True)
     return Workload("C2", mol, q, True, nocc)
 
@@ -187,10 +244,18 @@ def c5(seed: int = 0, natom: int = 60) -> Workload:
 
 
 def small(natom: int, ls: list[int], seed: int = 0, nocc: int | None = None,
-          lo: float = 0.1, hi: float = 1.0e3, complex_: bool = False) -> Workload:
-    """A reduced molecule with the same recipe (for parity at oracle-sized inputs)."""
+          lo: float = 0.1, hi: float = 1.0e3, complex_: bool = False, spherical: bool = False,
+          general: bool = False) -> Workload:
+    """A reduced molecule with the same recipe (for parity at oracle-sized
+    inputs); ``spherical``: d shells spherical; ``general``: the general
+    contraction variant."""
     rng = np.random.default_rng(seed)
-    mol = make_molecule(natom, ls, lo, hi, rng)
+    if general:
+        mol = general_molecule(natom, ls, lo, hi, rng, spherical=spherical)
+    else:
+        mol = make_molecule(natom, ls, lo, hi, rng)
+        if spherical:
+            mol = mol.as_spherical()
     n = mol.nbf
     if nocc is None:
         nocc = max(1, n // 4)

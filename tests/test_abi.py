@@ -78,3 +78,45 @@ def test_thresholds_flags():
     from paper_1905_01381_amd import cq
     assert cq.thresholds().flags == cq.CQ_DETERMINISTIC
     assert cq.thresholds(accumulate=True).flags == cq.CQ_DETERMINISTIC | cq.CQ_ACCUMULATE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcq.so not built")
+def test_general_basis_argument_errors():
+    """cq_basis_create_general refuses l = 3 (CQ_EUNSUPPORTED) and ncontr or
+    pure outside their ranges (CQ_EINVAL) before touching the device."""
+    import numpy as np
+    from paper_1905_01381_amd import cq, inputs
+    L = cq.lib()
+    mol = inputs.small(1, [0, 1, 2], seed=1).mol
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    xyz = np.ascontiguousarray(mol.shell_xyz, dtype=np.float64)
+    a = np.ascontiguousarray(mol.alpha)
+    c = np.ascontiguousarray(mol.coef)
+    npr = np.ascontiguousarray(mol.nprim, dtype=np.int32)
+    nsm = np.array([3], np.int32)
+
+    def create(ls, nco, pure):
+        ls, nco, pure = (np.ascontiguousarray(v, dtype=np.int32) for v in (ls, nco, pure))
+        h = ctypes.c_void_p()
+        return L.cq_basis_create_general(1, nsm.ctypes.data_as(ip), xyz.ctypes.data_as(dp), ls.ctypes.data_as(ip),
+                                         npr.ctypes.data_as(ip), nco.ctypes.data_as(ip), pure.ctypes.data_as(ip),
+                                         a.ctypes.data_as(dp), c.ctypes.data_as(dp), None, ctypes.byref(h))
+    assert create([0, 1, 3], [1, 1, 1], [0, 0, 1]) == cq.CQ_EUNSUPPORTED
+    assert b"l=3" in L.cq_last_error()
+    assert create([0, 1, 2], [1, 0, 1], [0, 0, 1]) == cq.CQ_EINVAL
+    assert create([0, 1, 2], [1, 65, 1], [0, 0, 1]) == cq.CQ_EINVAL
+    assert create([0, 1, 2], [1, 1, 1], [0, 0, 2]) == cq.CQ_EINVAL
+
+
+def test_general_recipe_counts():
+    """The spherical and general-contraction variants of the input recipe:
+    3s2p1d gives 14 functions per atom with spherical d (nbf 560 for the
+    40-atom two-component workload), the general variant keeps the function
+    count with one shell per angular momentum."""
+    import numpy as np
+    from paper_1905_01381_amd import inputs
+    assert inputs.c2(spherical=True).mol.nbf == 560
+    m = inputs.general_molecule(2, inputs.SHELLS_3S2P1D, 0.1, 1e3, np.random.default_rng(0))
+    assert list(m.shell_l) == [0, 1, 2] * 2
+    assert list(m.ncontr) == [3, 2, 1] * 2 and list(m.nprim) == [8, 6, 3] * 2
+    assert m.nbf == 28 and m.coef.size == 2 * (24 + 12 + 3)

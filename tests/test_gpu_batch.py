@@ -121,11 +121,22 @@ def test_autotune_keeps_results(ragged, torch_cuda):
     assert [p["cls"] for p in plan] == [p["cls"] for p in before]
     for p in plan:
         assert p["cl"] >= 1 and p["grid"] in (0, 2048) and p["tasks"] > 0 and p["ms"] > 0
+        assert p["acc"] in (-1, 0, 1, 2) and p["rot"] in (0, 1)
     J, K0, K1 = _batch_jk(torch, gb, Ps, As)
     for i in range(len(ws)):
         assert rel_err(J[i], J0[i]) < 1e-13
         assert rel_err(K0[i], K00[i]) < 1e-13
         assert rel_err(K1[i], K10[i]) < 1e-13
+    # the same plan set on a fresh handle forms the same partial sums: bitwise equal
+    g2 = cq.Basis.from_molecules([w.mol for w in ws])
+    g2.set_plan(plan)
+    assert [(p["cls"], p["cl"], p["grid"], p["exchanged"], p["acc"], p["rot"]) for p in g2.plan()] == \
+        [(p["cls"], p["cl"], p["grid"], p["exchanged"], p["acc"], p["rot"]) for p in plan]
+    J2, K02, K12 = _batch_jk(torch, g2, Ps, As)
+    for i in range(len(ws)):
+        assert np.array_equal(J2[i], J[i]) and np.array_equal(K02[i], K0[i]) and np.array_equal(K12[i], K1[i]), i
+    with pytest.raises(cq.CqError):
+        g2.set_plan([dict(plan[0], cl=65)])
 
 
 def test_batch_routed_modes(ragged, torch_cuda):

@@ -1,0 +1,169 @@
+"""Spherical d shells and generally contracted shells (paper: Introduction,
+contracted Gaussian basis functions with segmented or general contraction)
+through cq_basis_create_general, against the oracle's spherical basis on
+the same seeded inputs.  Tolerances as for the Cartesian path: J/K within
+1e-10 relative per matrix, one-electron integrals within 1e-12."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import scf as oscf
+from oracle import spherical as osph
+from oracle import twocomp
+from paper_1905_01381_amd import inputs
+from tests.gpu_common import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_JK = 1e-10
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.name}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1905_01381_amd import cq
+    cq.lib()
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def general_case(torch_cuda):
+    """2 atoms of the general-contraction recipe with spherical d: one s
+    shell with 3 contractions over 8 exponents, one p shell with 2 over 6,
+    one spherical d shell; nbf 2 * (3 + 6 + 5) = 28."""
+    from paper_1905_01381_amd import cq
+    w = inputs.small(2, inputs.SHELLS_3S2P1D, seed=21, lo=0.3, hi=50.0, spherical=True, general=True)
+    ob = osph.SphericalBasis.from_molecule(w.mol)
+    gb = cq.Basis.from_molecule(w.mol)
+    return w, ob, gb
+
+
+def test_general_spherical_full_parity(general_case, torch_cuda):
+    torch = torch_cuda
+    w, ob, gb = general_case
+    assert gb.nbf == ob.nbf == w.mol.nbf == 28
+    assert gb.nshell == ob.nshell == 2 * (3 + 2 + 1)
+    S = ob.overlap()
+    P = oracle.density_real(S, w.orbitals)
+    rng = np.random.default_rng(5)
+    A = inputs.random_symmetric(gb.nbf, rng, sign=-1)
+    G = rng.standard_normal((gb.nbf, gb.nbf))
+    r = gb.jk([_dev(torch, P), _dev(torch, A), _dev(torch, G)], sym=[1, -1, 0], want_j=[True, False, True])
+    torch.cuda.synchronize()
+    Jr, Kr = ob.jk_full(np.array([P, A, G]))
+    assert rel_err(r.J[0].cpu().numpy(), Jr[0]) < TOL_JK
+    assert rel_err(r.K[0].cpu().numpy(), Kr[0]) < TOL_JK
+    assert rel_err(r.K[1].cpu().numpy(), Kr[1]) < TOL_JK
+    assert rel_err(r.J[2].cpu().numpy(), Jr[2]) < TOL_JK
+    assert rel_err(r.K[2].cpu().numpy(), Kr[2]) < TOL_JK
+
+
+def test_general_spherical_one_electron(general_case, torch_cuda):
+    w, ob, gb = general_case
+    for kind in ("overlap", "kinetic"):
+        assert rel_err(gb.one_electron(kind).cpu().numpy(), ob.one_electron(kind)) < 1e-12, kind
+    got = gb.one_electron("dipole", direction=1, origin=(0.3, -0.2, 0.1)).cpu().numpy()
+    ref = ob.one_electron("dipole", direction=1, origin=(0.3, -0.2, 0.1))
+    assert rel_err(got, ref) < 1e-12
+    mol = w.mol
+    got = gb.one_electron("nuclear", charges=mol.charges, centers=mol.atoms).cpu().numpy()
+    ref = ob.one_electron("nuclear", charges=mol.charges, centers=mol.atoms)
+    assert rel_err(got, ref) < 1e-12
+    assert np.allclose(np.diag(gb.one_electron("overlap").cpu().numpy()), 1.0, atol=1e-13)
+
+
+def test_spherical_two_component(torch_cuda):
+    """cq_fock2e_2c on a spherical basis (3 atoms, 3s2p1d, nbf 42)."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.small(3, inputs.SHELLS_3S2P1D, seed=4, lo=0.3, hi=50.0, complex_=True, spherical=True)
+    ob = osph.SphericalBasis.from_molecule(w.mol)
+    P2 = oracle.density_2c(ob.overlap(), w.orbitals)
+    gb = cq.Basis.from_molecule(w.mol)
+    assert gb.nbf == 42
+    G = gb.fock2e_2c(_dev(torch, P2))
+    torch.cuda.synchronize()
+    Gr, _ = twocomp.fock2e(ob, P2)
+    assert rel_err(G.cpu().numpy(), Gr) < TOL_JK
+
+
+def test_spherical_c2_fullsize_sampled_blocks(torch_cuda):
+    """The two-component workload with spherical d (40 atoms, nbf 560): one
+    cq_fock2e_2c build, checked on sampled shell blocks from the oracle,
+    relative to the largest element of the whole matrix (the per-matrix
+    tolerance; the spin-coupling blocks of a d-d pair are 1e-3 of it)."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.c2(spherical=True)
+    ob = osph.SphericalBasis.from_molecule(w.mol)
+    P2 = oracle.density_2c(ob.overlap(), w.orbitals)
+    gb = cq.Basis.from_molecule(w.mol)
+    assert gb.nbf == 560
+    G = gb.fock2e_2c(_dev(torch, P2)).cpu().numpy()
+    n = gb.nbf
+    gmax = np.abs(G).max()
+    stack, _ = twocomp.real_parts(twocomp.split(P2))
+    o = ob.offsets
+    ls = ob.shell_l
+    d_sh = int(np.where(ls == 2)[0][7])
+    p_sh = int(np.where(ls == 1)[0][30])
+    s_sh = int(np.where(ls == 0)[0][50])
+    for a, b in [(d_sh, p_sh), (s_sh, d_sh), (d_sh, int(np.where(ls == 2)[0][20]))]:
+        jb = ob.j_block(a, b, stack[:1])[0]
+        kb = ob.k_block(a, b, stack)
+        Kc = [kb[I] + 1j * kb[4 + I] for I in range(4)]
+        Gc = [2 * jb - Kc[0], -Kc[1], -Kc[2], -Kc[3]]
+        blocks = {(0, 0): Gc[0] + Gc[3], (0, 1): Gc[1] - 1j * Gc[2], (1, 0): Gc[1] + 1j * Gc[2], (1, 1): Gc[0] - Gc[3]}
+        for (s, t), ref in blocks.items():
+            got = G[s * n + o[a]: s * n + o[a + 1], t * n + o[b]: t * n + o[b + 1]]
+            err = np.abs(got - ref).max() / gmax
+            assert err < TOL_JK, (a, b, s, t, err)
+
+
+def test_spherical_general_batch(torch_cuda):
+    """A batch handle over molecules of both kinds (general + spherical,
+    spherical only, Cartesian) against the oracle molecule by molecule."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    ws = [inputs.small(2, inputs.SHELLS_3S2P1D, seed=31, lo=0.3, hi=50.0, spherical=True, general=True),
+          inputs.small(3, inputs.SHELLS_3S2P1D, seed=32, lo=0.3, hi=50.0, spherical=True),
+          inputs.small(2, inputs.SHELLS_2S1P, seed=33, lo=0.15, hi=30.0)]
+    mols = [w.mol for w in ws]
+    gb = cq.Basis.from_molecules(mols)
+    obs = [osph.SphericalBasis.from_molecule(m) for m in mols]
+    assert gb.mol_nbf == [ob.nbf for ob in obs] == [28, 42, 10]
+    Ps = [oracle.density_real(ob.overlap(), w.orbitals) for ob, w in zip(obs, ws)]
+    r = gb.jk([gb.pack([_dev(torch, P) for P in Ps])])
+    torch.cuda.synchronize()
+    Js, Ks = gb.unpack(r.J[0]), gb.unpack(r.K[0])
+    for i, (ob, P) in enumerate(zip(obs, Ps)):
+        Jr, Kr = ob.jk(P)
+        assert rel_err(Js[i].cpu().numpy(), Jr) < TOL_JK, i
+        assert rel_err(Ks[i].cpu().numpy(), Kr) < TOL_JK, i
+
+
+def test_spherical_rhf_against_oracle(torch_cuda):
+    """The library's RS driver on a spherical, generally contracted basis
+    (2 atoms of charge 1, 2 electrons) against the oracle's RHF."""
+    from paper_1905_01381_amd import cq, scf
+    w = inputs.small(2, inputs.SHELLS_3S2P1D, seed=41, lo=0.3, hi=50.0, spherical=True, general=True)
+    ob = osph.SphericalBasis.from_molecule(w.mol)
+    gb = cq.Basis.from_molecule(w.mol)
+    ref = oscf.rhf(ob, w.mol, 1)[4]
+    res = scf.scf(gb, w.mol, "RS", 1, conv=1e-11)
+    assert res.converged
+    assert abs((res.energy - res.e_nuc) - ref) < 1e-8

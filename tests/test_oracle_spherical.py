@@ -1,0 +1,185 @@
+"""Pins of the oracle's spherical-harmonic shells and general contraction
+(paper: Introduction, contracted Gaussian basis functions with segmented or
+general contraction)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spherical as sph
+from paper_1905_01381_amd import inputs
+from tests import quad
+
+
+def _laplacian(poly: dict) -> dict:
+    out: dict = {}
+    for (a, b, c), v in poly.items():
+        for k, e in enumerate((a, b, c)):
+            if e >= 2:
+                n = [a, b, c]
+                n[k] -= 2
+                out[tuple(n)] = out.get(tuple(n), 0) + v * e * (e - 1)
+    return {e: v for e, v in out.items() if v != 0}
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3, 4])
+def test_solid_harmonics_harmonic_homogeneous_independent(l):
+    """Each generated polynomial is homogeneous of degree l and solves
+    Laplace's equation; the 2l+1 of them are linearly independent."""
+    polys = sph.solid_harmonics(l)
+    assert len(polys) == 2 * l + 1
+    comps = sph.cart_components(l)
+    M = np.zeros((len(polys), len(comps)))
+    for m, p in enumerate(polys):
+        assert p, m
+        assert all(sum(e) == l for e in p)
+        assert _laplacian(p) == {}
+        for e, v in p.items():
+            M[m, comps.index(e)] = v
+    assert np.linalg.matrix_rank(M) == 2 * l + 1
+
+
+def test_low_orders_are_the_textbook_functions():
+    """m = -l..l: l = 1 gives y, z, x; l = 2 gives xy, yz, 3z^2 - r^2, xz,
+    x^2 - y^2 (each up to a positive factor)."""
+    def ratio(p, q):
+        k = next(iter(q))
+        r = p[k] / q[k]
+        assert r > 0 and p.keys() == q.keys()
+        assert all(abs(p[e] - r * q[e]) < 1e-12 for e in q)
+    expect1 = [{(0, 1, 0): 1}, {(0, 0, 1): 1}, {(1, 0, 0): 1}]
+    for p, q in zip(sph.solid_harmonics(1), expect1):
+        ratio(p, q)
+    expect2 = [{(1, 1, 0): 1}, {(0, 1, 1): 1}, {(0, 0, 2): 2, (2, 0, 0): -1, (0, 2, 0): -1}, {(1, 0, 1): 1},
+               {(2, 0, 0): 1, (0, 2, 0): -1}]
+    for p, q in zip(sph.solid_harmonics(2), expect2):
+        ratio(p, q)
+
+
+def _general_molecule(seed=3):
+    """Two atoms: a generally contracted spherical d (two contractions over
+    three exponents) and a segmented spherical d on atom 0; s, p and a
+    Cartesian d on atom 1."""
+    rng = np.random.default_rng(seed)
+    xyz = np.array([[0.0, 0.0, 0.0], [0.3, -0.4, 1.5]])
+    shells = [(0, 2, 2, 1), (0, 2, 1, 1), (1, 0, 1, 0), (1, 1, 2, 0), (1, 2, 1, 0)]  # atom, l, ncontr, pure
+    sx, sl, npr, nco, pu, al, co = [], [], [], [], [], [], []
+    for at, l, nc, p in shells:
+        sx.append(xyz[at])
+        sl.append(l)
+        npr.append(3)
+        nco.append(nc)
+        pu.append(p)
+        al.append(np.sort(rng.uniform(0.3, 8.0, 3))[::-1])
+        co.append(rng.uniform(0.1, 1.0, 3 * nc))
+    return dict(shell_xyz=np.array(sx), shell_l=np.array(sl), nprim=np.array(npr), ncontr=np.array(nco),
+                pure=np.array(pu), alpha=np.concatenate(al), coef=np.concatenate(co))
+
+
+def _explicit_functions(g):
+    """Every basis function as a list of (coefficient, exponent triple,
+    exponent, centre) primitive monomials, from the polynomial definitions
+    (solid harmonics written out, Cartesian monomials), unnormalized.  The
+    input coefficients multiply primitives scaled by (2a/pi)^{3/4} (4a)^{l/2}
+    (the library's input convention; constant factors drop out)."""
+    funcs = []
+    pa = pc = 0
+    for s in range(g["shell_l"].size):
+        l, n, nc, p = int(g["shell_l"][s]), int(g["nprim"][s]), int(g["ncontr"][s]), int(g["pure"][s])
+        A = g["shell_xyz"][s]
+        alpha = g["alpha"][pa:pa + n]
+        for k in range(nc):
+            c = g["coef"][pc + k * n:pc + (k + 1) * n]
+            polys = sph.solid_harmonics(l) if (p and l >= 2) else [{e: 1.0} for e in quad.cart_components(l)]
+            for poly in polys:
+                funcs.append([(v * ci * (2 * ai / np.pi) ** 0.75 * (4 * ai) ** (0.5 * l), e, ai, A)
+                              for e, v in poly.items() for ci, ai in zip(c, alpha)])
+        pa += n
+        pc += n * nc
+    return funcs
+
+
+def _quad_overlap(f, g):
+    return sum(cf * cg * quad.overlap_prim(ef, af, Af, eg, ag, Ag) for cf, ef, af, Af in f for cg, eg, ag, Ag in g)
+
+
+def test_spherical_and_general_overlap_by_quadrature():
+    """The oracle's overlap matrix of spherical, generally contracted shells
+    equals quadrature of the explicitly written functions, each normalized by
+    its own quadrature norm: this fixes the order, signs and coefficients of
+    the spherical combinations and the contraction-major order of a general
+    shell."""
+    g = _general_molecule()
+    B = sph.SphericalBasis(**g)
+    S = B.overlap()
+    funcs = _explicit_functions(g)
+    assert len(funcs) == B.nbf == 5 * 2 + 5 + 1 + 3 * 2 + 6
+    norms = np.array([np.sqrt(_quad_overlap(f, f)) for f in funcs])
+    for i, j in itertools.product(range(B.nbf), repeat=2):
+        if j < i:
+            continue
+        ref = _quad_overlap(funcs[i], funcs[j]) / (norms[i] * norms[j])
+        assert S[i, j] == pytest.approx(ref, abs=2e-13), (i, j)
+
+
+def test_spherical_block_orthonormal_and_free_of_r2():
+    """Within one contracted d shell the five spherical functions are
+    orthonormal under the oracle's contracted overlap and orthogonal to the
+    s-type combination x^2 + y^2 + z^2."""
+    mol = inputs.make_molecule(1, [2], 0.3, 20.0, np.random.default_rng(2))
+    C = oracle.Basis.from_molecule(mol)
+    Sdd = C.overlap()
+    T = sph.sph_transform(2)
+    assert np.allclose(T @ Sdd @ T.T, np.eye(5), atol=1e-13)
+    # r^2 g = sum over xx, yy, zz of ||x^2 g|| phi; the norms are equal
+    r2 = np.array([1.0, 0, 0, 1.0, 0, 1.0])
+    assert np.allclose(T @ Sdd @ r2, 0.0, atol=1e-13)
+
+
+def test_spherical_jk_rotation_invariant_energies():
+    """Rotating the molecule rigidly about the origin leaves Tr(P J[P]) and
+    Tr(P K[P]) of the ground-state-like density P = C C^T with C from the
+    lowest orbitals of the overlap-orthonormalized core (a function of the
+    geometry only) unchanged: a spherical transformation mixing in the wrong
+    functions would break the invariance."""
+    g = _general_molecule(seed=7)
+    def energies(xyz):
+        gg = dict(g, shell_xyz=xyz)
+        B = sph.SphericalBasis(**gg)
+        S = B.overlap()
+        Z = np.array([1.0, 1.0])
+        at = np.array([g["shell_xyz"][0], g["shell_xyz"][-1]])
+        R = xyz[[0, -1]]
+        h = B.one_electron("kinetic") + B.one_electron("nuclear", charges=Z, centers=R)
+        X = oracle.inv_sqrt(S)
+        w, v = np.linalg.eigh(X @ h @ X)
+        Cocc = X @ v[:, :3]
+        P = Cocc @ Cocc.T
+        J, K = B.jk(P)
+        return np.sum(P * J), np.sum(P * K), w[:4]
+    e0 = energies(g["shell_xyz"])
+    ang = 0.7
+    Rz = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(0.4), -np.sin(0.4)], [0, np.sin(0.4), np.cos(0.4)]])
+    e1 = energies(g["shell_xyz"] @ (Rx @ Rz).T)
+    assert e1[0] == pytest.approx(e0[0], rel=1e-11)
+    assert e1[1] == pytest.approx(e0[1], rel=1e-11)
+    assert np.allclose(e1[2], e0[2], rtol=1e-10, atol=1e-12)
+
+
+def test_general_contraction_with_one_contraction_is_segmented():
+    """ncontr = 1 everywhere and no spherical shell: the same matrices as the
+    segmented Cartesian oracle."""
+    mol = inputs.make_molecule(2, [0, 1, 2], 0.3, 20.0, np.random.default_rng(4))
+    n = mol.nshell
+    B = sph.SphericalBasis(mol.shell_xyz, mol.shell_l, mol.nprim, np.ones(n, int), np.zeros(n, int),
+                           mol.alpha, mol.coef)
+    C = oracle.Basis.from_molecule(mol)
+    assert np.array_equal(B.T, np.eye(C.nbf))
+    P = inputs.random_symmetric(C.nbf, np.random.default_rng(1))
+    J1, K1 = B.jk(P)
+    J2, K2 = C.jk(P)
+    # the oracle's threaded sums may round differently from call to call
+    assert np.allclose(J1, J2, rtol=0, atol=1e-13 * np.abs(J2).max())
+    assert np.allclose(K1, K2, rtol=0, atol=1e-13 * np.abs(K2).max())
