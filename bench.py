@@ -214,6 +214,8 @@ def _c5_state(a, torch, cq, inputs, natom):
     from paper_1905_01381_amd import scf
     w = inputs.c5(natom=natom)
     gb = cq.Basis.from_molecule(w.mol)
+    if natom >= 40:
+        gb.trace(True)  # a progress line per class (builds of seconds)
     t0 = time.perf_counter()
     res = scf.rhf(gb, w.mol, natom // 2)
     _log(f"{natom} atoms, nbf {gb.nbf}; RHF E = {res.energy:.8f} in {res.iterations} iterations "
