@@ -367,6 +367,20 @@ cq_status cq_rt_set_params(cq_rt rt, double sc_tol, int max_iter, double accept_
  * an EM2 step from P_k when n % period == 0 or no P_{k-1} exists yet, a
  * leap-frog step otherwise.  period >= 1 (default 1000). */
 cq_status cq_rt_set_restart(cq_rt rt, int period);
+/* External one-body perturbation (paper: "Real-Time Electronic Dynamics",
+ * Eq. td_pert and the envelope list after it): F(P, t) = F_0(P) + f(t) V with
+ * V the dipole matrix Dz given to cq_rt_create (a length-gauge electric
+ * field along that operator) and
+ *   f(t) = kappa g(t - t_on) for t_on <= t < t_off, 0 otherwise,
+ *   g = 1 (envelope 1, step), u (2, linear ramp), cos(param u) (3, plane
+ *   wave, param = omega), exp(-param u^2) (4, Gaussian, param = alpha);
+ * envelope 0 removes the field (default).  Time t = (steps taken) x dt from
+ * creation.  The Fock matrix of a density is taken at its own time: EM2 at
+ * t_k and t_k + dt, the midpoint at t_k + dt/2, MMUT at t_k.  The energy
+ * observable includes the interaction, Re Tr P (h + f V + F).  A delta kick
+ * is applied by the caller to P0 before cq_rt_create.  CQ_EINVAL for an
+ * envelope outside 0..4, non-finite kappa or param, or t_off < t_on. */
+cq_status cq_rt_set_field(cq_rt rt, int envelope, double kappa, double param, double t_on, double t_off);
 /* Advance nsteps steps; per step (HOST arrays, each may be NULL): the
  * electronic energy Re Tr[P(h + F)] (costs one extra, uncounted build),
  * the electronic dipole -2 Re Tr[D_z P] (Eq. td_expectation), and the

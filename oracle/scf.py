@@ -8,9 +8,13 @@ from __future__ import annotations
 import numpy as np
 
 
-def rhf(basis, mol, nocc, maxiter=200, conv=1e-11):
+def rhf(basis, mol, nocc, maxiter=200, conv=1e-11, h_add=None):
+    """h_add: a static one-body term added to the core Hamiltonian (e.g. a
+    field kappa V)."""
     S = basis.overlap()
     h = basis.one_electron("kinetic") + basis.one_electron("nuclear", charges=mol.charges, centers=mol.atoms)
+    if h_add is not None:
+        h = h + h_add
     w, U = np.linalg.eigh(S)
     X = (U / np.sqrt(w)) @ U.T
 

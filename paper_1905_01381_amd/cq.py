@@ -80,6 +80,7 @@ def lib():
         L.cq_rt_set_mode.argtypes = [vp, i]
         L.cq_rt_set_params.argtypes = [vp, ctypes.c_double, i, ctypes.c_double]
         L.cq_rt_set_restart.argtypes = [vp, i]
+        L.cq_rt_set_field.argtypes = [vp, i, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.cq_rt_step.argtypes = [vp, i, dp, dp, ip]
         L.cq_rt_density.argtypes = [vp, vp, vp]
         L.cq_rt_stats.argtypes = [vp, llp]
@@ -100,7 +101,7 @@ def lib():
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
                      "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
-                     "cq_mlp_eval", "cq_mlp_adam", "cq_sync_status", "cq_jk_size_check", "cq_jk_build_noalloc", "cq_rt_set_restart", "cq_zgemm"):
+                     "cq_mlp_eval", "cq_mlp_adam", "cq_sync_status", "cq_jk_size_check", "cq_jk_build_noalloc", "cq_rt_set_restart", "cq_rt_set_field", "cq_zgemm"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -436,6 +437,14 @@ class RT:
     def set_restart(self, period: int):
         """MMUT: EM2 seed/restart every `period` steps."""
         _check(lib().cq_rt_set_restart(self.h, int(period)))
+
+    FIELD_ENVELOPES = {"none": 0, "step": 1, "ramp": 2, "plane_wave": 3, "gaussian": 4}
+
+    def set_field(self, envelope: str = "none", kappa: float = 0.0, param: float = 0.0, t_on: float = 0.0,
+                  t_off: float = float("inf")):
+        """External perturbation f(t) Dz (see cq_rt_set_field)."""
+        _check(lib().cq_rt_set_field(self.h, self.FIELD_ENVELOPES[envelope], float(kappa), float(param),
+                                     float(t_on), float(t_off)))
 
     def step(self, nsteps: int, energy: bool = False, dipole: bool = True):
         E = np.zeros(nsteps)

@@ -358,7 +358,7 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
         for j in range(nb):
             s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
             out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s}));")
-            out(f"      if (dg.acc_lvl) {{ if (dj == 0) s_jab[(m * {na * nb} + {i * nb + j}) * 8 + bi] += s; }}")
+            out(f"      if (dg.acc_lvl) {{ if (dj == 0) s_jab[(js * {na * nb} + {i * nb + j}) * 8 + bi] += s; }}")
             out(f"      else if (dj == 0 && rowv) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     for k in range(nc):
         for l in range(nd):
@@ -386,7 +386,7 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
             out(f"    {{ const {T_()} s = {red('red_i')}({s});")
-            out(f"      if (dg.acc_lvl) {{ if (bi == 0) s_kad[(m * {na * nd} + {i * nd + l}) * 8 + dj] += s; }}")
+            out(f"      if (dg.acc_lvl) {{ if (bi == 0) s_kad[(ks * {na * nd} + {i * nd + l}) * 8 + dj] += s; }}")
             out(f"      else if (bi == 0 && colv) acc_k(mc, kidx(dg, mc, fa + {i}, fd + {l}, ks), s); }}")
     for j in range(nb):
         for k in range(nc):
@@ -400,7 +400,7 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
             s = " + ".join(f"{V(i, j, k, l)} * xac{i}{k}" for i in range(na) for k in range(nc))
             out(f"    {{ const {T_()} s = {s};")
             out(f"      if (dg.acc_lvl < 2) {{ if (active) acc_k(mc, kidx(dg, mc, fb + {j}, fd + {l}, ks), s); }}")
-            out(f"      else s_kbd[(m * {nb * nd} + {j * nd + l}) * 64 + lane] += s; }}")
+            out(f"      else s_kbd[(ks * {nb * nd} + {j * nd + l}) * 64 + lane] += s; }}")
     out("  }")
     out("}")
 
@@ -839,10 +839,10 @@ def emit_acc_zero(o: Emitter, la, lb, lc, ld):
     kbd = acc_doubles(la, lb, lc, ld) // 64
     nab, nad = ncart(la) * ncart(lb), ncart(la) * ncart(ld)
     o("    if (dg.acc_lvl >= 2)")
-    o(f"      for (int t = 0; t < {kbd} * dg.nX; ++t) s_kbd[t * 64 + lane] = 0.0;")
+    o(f"      for (int t = 0; t < {kbd} * dg.nK; ++t) s_kbd[t * 64 + lane] = 0.0;")
     o("    if (dg.acc_lvl) {")
-    o(f"      if (dj == 0) for (int t = 0; t < {nab} * dg.nX; ++t) s_jab[t * 8 + bi] = 0.0;")
-    o(f"      if (bi == 0) for (int t = 0; t < {nad} * dg.nX; ++t) s_kad[t * 8 + dj] = 0.0;")
+    o(f"      if (dj == 0) for (int t = 0; t < {nab} * dg.nJ; ++t) s_jab[t * 8 + bi] = 0.0;")
+    o(f"      if (bi == 0) for (int t = 0; t < {nad} * dg.nK; ++t) s_kad[t * 8 + dj] = 0.0;")
     o("    }")
 
 
@@ -855,13 +855,13 @@ def emit_acc_flush(o: Emitter, la, lb, ld):
     o("        if (js >= 0 && dj == 0 && rowv) {")
     for i in range(na):
         for j in range(nb):
-            o(f"          {{ const double s = s_jab[(m * {na * nb} + {i * nb + j}) * 8 + bi];")
+            o(f"          {{ const double s = s_jab[(js * {na * nb} + {i * nb + j}) * 8 + bi];")
             o(f"            if (s != 0.0) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     o("        }")
     o("        if (ks >= 0 && bi == 0 && fdv >= 0) {")
     for i in range(na):
         for l in range(nd):
-            o(f"          {{ const double s = s_kad[(m * {na * nd} + {i * nd + l}) * 8 + dj];")
+            o(f"          {{ const double s = s_kad[(ks * {na * nd} + {i * nd + l}) * 8 + dj];")
             o(f"            if (s != 0.0) acc_k(mc, kidx(dg, mc, fa + {i}, fdv + {l}, ks), s); }}")
     o("        }")
     o("      }")
@@ -872,7 +872,7 @@ def emit_acc_flush(o: Emitter, la, lb, ld):
     o("        if (ks < 0) continue;")
     for j in range(nb):
         for l in range(nd):
-            o(f"        {{ const double s = s_kbd[(m * {nb * nd} + {j * nd + l}) * 64 + lane];")
+            o(f"        {{ const double s = s_kbd[(ks * {nb * nd} + {j * nd + l}) * 64 + lane];")
             o(f"          if (s != 0.0) acc_k(mc, kidx(dg, mc, fb + {j}, fdv + {l}, ks), s); }}")
     o("      }")
     o("    }")
@@ -916,12 +916,13 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     emit_boys_lds(o, L, f32)
     kbd = acc_doubles(la, lb, lc, ld)
     if kbd:
-        # task accumulators, sized at launch: K'_bd [nbd][nX][64 lanes] (level 2),
-        # then J'_ab [nab][nX][8 rows] and K'_ad [nad][nX][8 columns] (level >= 1)
+        # task accumulators, sized at launch by the Coulomb / exchange slots of
+        # the build: K'_bd [nK][nbd][64 lanes] (level 2), then
+        # J'_ab [nJ][nab][8 rows] and K'_ad [nK][nad][8 columns] (level >= 1)
         o("  extern __shared__ double s_acc[];")
         o(f"  double* const s_kbd = s_acc;")
-        o(f"  double* const s_jab = s_acc + (dg.acc_lvl >= 2 ? {kbd} * dg.nX : 0);")
-        o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * 8} * dg.nX;")
+        o(f"  double* const s_jab = s_acc + (dg.acc_lvl >= 2 ? {kbd} * dg.nK : 0);")
+        o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * 8} * dg.nJ;")
     o("  const int lane = threadIdx.x;")
     o("  const int bi = lane >> 3, dj = lane & 7;")
     sacc = staged_acc_doubles(la, lb, lc, ld)

@@ -122,12 +122,14 @@ __global__ void k_split_re_im(const double2* __restrict__ P, double* __restrict_
     }
 }
 
-// F = h + 2 J - K_re - i K_im  (closed shell, per-spin density)
-__global__ void k_fock(const double* __restrict__ h, const double* __restrict__ J, const double* __restrict__ Kr,
-                       const double* __restrict__ Ki, double2* __restrict__ F, long long n)
+// F = h + f V + 2 J - K_re - i K_im  (closed shell, per-spin density; f V the
+// external perturbation at the Fock matrix's time, Eq. td_pert)
+__global__ void k_fock(const double* __restrict__ h, const double* __restrict__ V, double f,
+                       const double* __restrict__ J, const double* __restrict__ Kr, const double* __restrict__ Ki,
+                       double2* __restrict__ F, long long n)
 {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
-        F[t] = make_double2(h[t] + 2.0 * J[t] - Kr[t], -Ki[t]);
+        F[t] = make_double2(h[t] + f * V[t] + 2.0 * J[t] - Kr[t], -Ki[t]);
 }
 
 // Hermitian part: A <- (A + A^dagger) / 2
@@ -521,6 +523,10 @@ struct cq_rt_s {
     double sc_tol = 1e-10, acc_tol = 1e-10;
     int max_iter = 30;
     int restart = 1000;  // MMUT: EM2 restart period (steps)
+    // external perturbation f(t) V with V the dipole operator (Eq. td_pert):
+    // envelope 0 none, 1 step, 2 linear ramp, 3 plane wave, 4 Gaussian
+    int env = 0;
+    double kappa = 0, fparam = 0, t_on = 0, t_off = 0;
     long long steps = 0, builds = 0, accepted = 0, fallbacks = 0;
     // MLP
     float *w = nullptr, *gw = nullptr, *am = nullptr, *av = nullptr, *xs = nullptr, *lossd = nullptr;
@@ -597,8 +603,24 @@ static cq_status expm(cq_rt_s* r, const double2* H, double dt, double2* U)
     return CQ_OK;
 }
 
-// orthonormal P' -> AO Fock (complex) and orthonormal F' into Fo
-static cq_status fock(cq_rt_s* r, const double2* Po, double2* Fo_out)
+// f(t) = kappa g(t - t_on) inside [t_on, t_off), 0 outside
+static double field_at(const cq_rt_s* r, double t)
+{
+    if (r->env == 0 || t < r->t_on || t >= r->t_off) return 0.0;
+    const double u = t - r->t_on;
+    switch (r->env) {
+    case 1: return r->kappa;
+    case 2: return r->kappa * u;
+    case 3: return r->kappa * std::cos(r->fparam * u);
+    default: return r->kappa * std::exp(-r->fparam * u * u);
+    }
+}
+
+// time of the newest density
+static double now(const cq_rt_s* r) { return (double)r->steps * r->dt; }
+
+// orthonormal P' -> AO Fock (complex) at time t and orthonormal F' into Fo
+static cq_status fock(cq_rt_s* r, const double2* Po, double2* Fo_out, double t)
 {
     const long long nn = (long long)r->n * r->n;
     cq_status st;
@@ -612,7 +634,8 @@ static cq_status fock(cq_rt_s* r, const double2* Po, double2* Fo_out)
     double* Kp[2] = {r->Kr, r->Ki};
     if ((st = cq_jk_build(r->b, 2, P, sym, Jp, Kp, nullptr, r->stream))) return st;
     r->builds++;
-    hipLaunchKernelGGL(k_fock, grid1(nn), dim3(256), 0, r->stream, r->h, r->J, r->Kr, r->Ki, r->Fao, nn);
+    hipLaunchKernelGGL(k_fock, grid1(nn), dim3(256), 0, r->stream, r->h, r->Dz, field_at(r, t), r->J, r->Kr, r->Ki,
+                       r->Fao, nn);
     // F' = X F X
     if ((st = mm(r, r->T1, r->Xc, r->Fao, false))) return st;
     if ((st = mm(r, Fo_out, r->T1, r->Xc, false))) return st;
@@ -653,10 +676,11 @@ static void push_history(cq_rt_s* r, double2* Pnew)
 static cq_status step_em2(cq_rt_s* r)
 {
     cq_status st;
-    if ((st = fock(r, r->hist[0], r->Fo))) return st;
+    const double t = now(r);
+    if ((st = fock(r, r->hist[0], r->Fo, t))) return st;
     if ((st = expm(r, r->Fo, r->dt, r->U))) return st;
     if ((st = transform(r, r->U, r->hist[0], r->Pguess))) return st;
-    if ((st = fock(r, r->Pguess, r->Fo2))) return st;
+    if ((st = fock(r, r->Pguess, r->Fo2, t + r->dt))) return st;
     const long long nn = (long long)r->n * r->n;
     hipLaunchKernelGGL(k_axpby, grid1(nn), dim3(256), 0, r->stream, r->Fo2, r->Fo, 0.5, 0.5, nn);
     if ((st = expm(r, r->Fo2, r->dt, r->U))) return st;
@@ -670,8 +694,9 @@ static cq_status midpoint_iterate(cq_rt_s* r, bool learned)
 {
     const long long nn = (long long)r->n * r->n;
     cq_status st;
+    const double tm = now(r) + 0.5 * r->dt;
     for (int it = 0; it < r->max_iter; ++it) {
-        if ((st = fock(r, r->Pmid, r->Fo))) return st;
+        if ((st = fock(r, r->Pmid, r->Fo, tm))) return st;
         if ((st = expm(r, r->Fo, r->dt, r->U))) return st;
         if ((st = transform(r, r->U, r->hist[0], r->Pnext))) return st;
         // new midpoint (P_k + P_{k+1}) / 2 into Pguess; compare with Pmid
@@ -727,7 +752,7 @@ static cq_status step_mmut(cq_rt_s* r)
 {
     if (r->nhist < 2 || r->steps % r->restart == 0) return step_em2(r);
     cq_status st;
-    if ((st = fock(r, r->hist[0], r->Fo))) return st;
+    if ((st = fock(r, r->hist[0], r->Fo, now(r)))) return st;
     if ((st = expm(r, r->Fo, 2.0 * r->dt, r->U))) return st;
     if ((st = transform(r, r->U, r->hist[1], r->Pnext))) return st;
     push_history(r, r->Pnext);
@@ -735,14 +760,15 @@ static cq_status step_mmut(cq_rt_s* r)
 }
 
 // Dipole -2 Re Tr(D_z P) of the newest density; with want_energy also the
-// electronic energy Re Tr(P (h + F(P))) from one extra Fock build that is not
-// counted among the propagation builds.
+// electronic energy Re Tr(P (h_t + F(P, t))), h_t = h + f(t) V, from one extra
+// Fock build that is not counted among the propagation builds.
 static cq_status observables(cq_rt_s* r, bool want_energy, double* E, double* mu)
 {
     const long long nn = (long long)r->n * r->n;
     cq_status st;
+    const double t = now(r);
     if (want_energy) {
-        if ((st = fock(r, r->hist[0], r->Fo2))) return st;
+        if ((st = fock(r, r->hist[0], r->Fo2, t))) return st;
         r->builds--;
     } else {
         if ((st = mm(r, r->T1, r->Xc, r->hist[0], false))) return st;
@@ -761,7 +787,7 @@ static cq_status observables(cq_rt_s* r, bool want_energy, double* E, double* mu
     hipLaunchKernelGGL(k_dot_herm, dim3(nb), dim3(256), 0, r->stream, r->Pao, r->Fao, nn, r->red);
     double ef = 0;
     if ((st = host_reduce(r, nb, false, &ef))) return st;
-    *E = eh + ef;
+    *E = eh + field_at(r, t) * d + ef;
     return CQ_OK;
 }
 
@@ -859,6 +885,20 @@ extern "C" cq_status cq_rt_set_mode(cq_rt r, int mode)
 {
     if (!r || mode < 0 || mode > 3) return cq_internal_fail(CQ_EINVAL, "bad mode");
     r->mode = mode;
+    return CQ_OK;
+}
+
+extern "C" cq_status cq_rt_set_field(cq_rt r, int envelope, double kappa, double param, double t_on, double t_off)
+{
+    if (!r) return cq_internal_fail(CQ_EINVAL, "rt is NULL");
+    if (envelope < 0 || envelope > 4) return cq_internal_fail(CQ_EINVAL, "envelope must be 0..4");
+    if (!std::isfinite(kappa) || !std::isfinite(param) || std::isnan(t_on) || std::isnan(t_off) || !(t_off >= t_on))
+        return cq_internal_fail(CQ_EINVAL, "field parameters must be finite with t_off >= t_on");
+    r->env = envelope;
+    r->kappa = kappa;
+    r->fparam = param;
+    r->t_on = t_on;
+    r->t_off = t_off;
     return CQ_OK;
 }
 
