@@ -63,6 +63,7 @@ def parse():
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l"])
+    ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (default plan only)")
     ap.add_argument("--serialize", action="store_true",
                     help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
                          "kernel-trace profiler so that each kernel's duration is its own")
@@ -178,11 +179,16 @@ def bench_c4(a, torch, cq, inputs):
          f"{gb.mol_nbf[-1]}, {counts:.3e} quartets")
     t_default = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
     _log(f"c4 batched default plan: {t_default:.3f} s/build")
-    t0 = time.perf_counter()
-    plan = gb.autotune(nmat=1, reps=1)
-    t_tune = time.perf_counter() - t0
-    t_tuned = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
-    _log(f"c4 batched tuned plan: {t_tuned:.3f} s/build (autotune {t_tune:.1f} s)")
+    if a.no_tune:
+        # cq_autotune times every candidate on the whole batch: about 30
+        # launches per class, too long for batches of minutes per build
+        plan, t_tune, t_tuned = gb.plan(), 0.0, t_default
+    else:
+        t0 = time.perf_counter()
+        plan = gb.autotune(nmat=1, reps=1)
+        t_tune = time.perf_counter() - t0
+        t_tuned = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
+        _log(f"c4 batched tuned plan: {t_tuned:.3f} s/build (autotune {t_tune:.1f} s)")
     singles = [cq.Basis.from_molecule(w.mol) for w in ws]
 
     def per_mol():
@@ -191,7 +197,8 @@ def bench_c4(a, torch, cq, inputs):
     t_single = _timed(torch, per_mol, a.steps, a.warmup)
     _log(f"c4 one handle per molecule: {t_single:.3f} s/build")
     return {
-        "metric": "J+K builds/sec, batched uneven launch (all molecules per class launch, autotuned)",
+        "metric": "J+K builds/sec, batched uneven launch (all molecules per class launch, "
+                  + ("default plan)" if a.no_tune else "autotuned)"),
         "value": 1.0 / t_tuned, "unit": "builds/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": t_tuned * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
@@ -204,6 +211,7 @@ def bench_c4(a, torch, cq, inputs):
         "speedup_batched_tuned_vs_per_molecule": t_single / t_tuned,
         "speedup_tuned_vs_default": t_default / t_tuned,
         "autotune_s": t_tune,
+        "tuned": not a.no_tune,
         "plan": [{"cls": "".join("spd"[x] for x in p["cls"]), "cl": p["cl"], "grid": p["grid"], "exchanged": p["exchanged"],
                   "acc": p["acc"], "rot": p["rot"],
                   "ms": round(p["ms"], 3)} for p in plan],

@@ -776,7 +776,10 @@ HEADER = """// Generated by gen_eri.py -- do not edit.  Per-class Obara-Saika /
 # region.  Measured on the 40-atom 3s2p1d two-component build: (dp|pp)
 # 110.8 -> 82.0 ms and (dp|dp) 84.5 -> 83.1 ms (two waves per SIMD); the
 # one-wave classes, which cannot hide the read-modify-write latency behind
-# another wave, were 3-8 % slower and keep the per-step flush.
+# another wave, were 3-8 % slower and keep the per-step flush; longer c
+# ranges (4 to 32 steps per task, fewer flushes per quartet) did not bring
+# them back to the per-step flush either ((dd|dp): 105 ms at the default
+# range, 98 ms at 16 steps, against 97 ms without the accumulators).
 STAGE_ACC_CLASSES = {(2, 1, 1, 1), (2, 1, 2, 1)}
 
 
