@@ -411,13 +411,14 @@ def cpu_baseline(w, budget_s: float):
     stack, _ = twocomp.real_parts(twocomp.split(P2))
     ls = w.mol.shell_l
     ns = ob.nshell
-    picks = [(int(np.where(ls == 2)[0][3]), int(np.where(ls == 1)[0][11])),
-             (int(np.where(ls == 2)[0][30]), int(np.where(ls == 2)[0][12])),
-             (int(np.where(ls == 1)[0][70]), int(np.where(ls == 2)[0][5])),
-             (int(np.where(ls == 2)[0][17]), int(np.where(ls == 0)[0][60])),
-             (int(np.where(ls == 1)[0][40]), int(np.where(ls == 0)[0][7])),
-             (int(np.where(ls == 0)[0][90]), int(np.where(ls == 2)[0][20])),
-             (int(np.where(ls == 0)[0][3]), int(np.where(ls == 0)[0][5]))]
+    # seeded (a, c) shell pairs, every pair of angular momenta in turn; the
+    # loop below stops at the time budget
+    rng = np.random.default_rng(11)
+    by_l = [np.where(ls == l)[0] for l in range(3)]
+    picks = []
+    for k in range(90):
+        la, lc = (k // 3) % 3, k % 3
+        picks.append((int(rng.choice(by_l[la])), int(rng.choice(by_l[lc]))))
     t0 = time.time()
     nq = 0
     done = 0

@@ -282,10 +282,13 @@ cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t strea
  *      that kernel exists) x task shapes (length of the c range one wave
  *      walks: the default, half, twice and four times it, at most 64) x grid
  *      caps (one wave per task, or 2048 waves looping over tasks);
- *   2. at the fastest of those, the walk rotation (tasks start their c walk
- *      at step task mod length, spreading the flushes of tasks that share a
- *      bra shell) and every LDS accumulator level below the highest that
- *      fits (less LDS per wave, more resident waves, more flushes);
+ *   2. at the fastest of those, the task order flags (bit 0: tasks start
+ *      their c walk at step task mod length, spreading the flushes of tasks
+ *      that share a bra shell; bit 1: the task list is dealt to the 8 XCDs
+ *      in runs of 8 consecutive tasks, so that tasks sharing shells share
+ *      an L2) and
+ *      every LDS accumulator level below the highest that fits (less LDS
+ *      per wave, more resident waves, more flushes);
  * and keeps the fastest for every later build on the handle.  Every plan is
  * deterministic; two plans agree to rounding only (the FP64 partial sums a
  * wave forms before its exact fixed-point additions depend on the plan).
@@ -294,7 +297,7 @@ cq_status cq_autotune(cq_basis b, int nmat, int reps, hipStream_t stream);
 
 /* The launch plan per class (tuned, set or default): for k < cap,
  * rec[10k..10k+9] = (la, lb, lc, ld, c-range length, grid cap or 0, tasks,
- * exchanged, LDS level or -1, rotation) and ms[k] = best time measured by
+ * exchanged, LDS level or -1, task order flags) and ms[k] = best time measured by
  * cq_autotune (0 if not tuned); *n = classes with work.  exchanged = 1: the
  * class runs with bra and ket pairs exchanged, (lc ld|la lb), which loops
  * over the other pair's first shell and flushes fewer exchange partial sums
@@ -307,7 +310,7 @@ cq_status cq_autotune_read(cq_basis b, int cap, int* rec, float* ms, int* n);
  * cq_autotune_read writes them (the tasks field is ignored), e.g. a plan
  * tuned earlier on the same molecules.  Every record is checked first
  * (class with work on this basis, c-range length 1..64, grid cap >= 0,
- * exchanged 0/1 and built, LDS level -1..2, rotation 0/1; CQ_EINVAL
+ * exchanged 0/1 and built, LDS level -1..2, task order flags 0..3; CQ_EINVAL
  * otherwise, nothing changed).  Re-uploads the classes' task lists
  * (allocates); not stream-ordered: no build may be in flight on the handle. */
 cq_status cq_plan_set(cq_basis b, int n, const int* rec);

@@ -198,7 +198,8 @@ struct Digest {
     double skip;          // density-weighted Schwarz threshold (0: none)
     const double* pmax;   // block-diagonal [ns][ns] per molecule: max |X| per shell block
     int nshell;
-    int rot;              // 1: each task starts its c walk at step (task mod length)
+    int rot;              // bit 0: each task starts its c walk at step (task mod length);
+                          // bit 1: tasks dealt to the 8 XCDs in contiguous eighths
     double* stage;        // per-wave private stage, [wave][class stage size][64]
     size_t stage_bytes;   // bytes of the stage workspace (caps the grid of staged classes)
     int mode;             // 0: FP64 everywhere; 1: precision-routed

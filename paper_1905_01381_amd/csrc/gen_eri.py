@@ -941,10 +941,20 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     # With screening or routing, the build's classification pass lists the
     # tasks that have steps of this kernel's precision and marks those steps
     # (bit c - c_lo of the task's mask); the kernel walks only them.
+    # With bit 1 of dg.rot (and a grid that is a multiple of 8) the tasks are
+    # dealt in runs of 8 consecutive tasks per XCD (the workgroups go to the
+    # 8 XCDs round robin): a run shares bra shells and density rows in one
+    # XCD's L2, and the runs stay short enough to keep the longest-first
+    # order balanced across the XCDs.
     o("  const bool listed = tm.list != nullptr;")
     o("  const int ntk = listed ? *tm.list_n : tm.ntask;")
-    o("  for (int it = blockIdx.x; it < ntk; it += gridDim.x) {")
-    o("    const int task = listed ? tm.list[it] : it;")
+    o("  const bool xo = (dg.rot & 2) && (gridDim.x & 7) == 0;")
+    o("  const int nit = xo ? (ntk + 63) & ~63 : ntk;")
+    o("  for (int it = blockIdx.x; it < nit; it += gridDim.x) {")
+    o("    // it = 64 g + 8 q + x (x: the XCD) -> task 64 g + 8 x + q")
+    o("    const int itx = xo ? (it & ~63) + ((it & 7) << 3) + ((it >> 3) & 7) : it;")
+    o("    if (itx >= ntk) continue;")
+    o("    const int task = listed ? tm.list[itx] : itx;")
     o(f"    const unsigned long long smask = listed ? tm.masks[2 * task + {1 if f32 else 0}] : ~0ull;")
     o("    const int4 tk = tm.tasks[task];")
     o("    const int4 tk2 = tm.tasks2[task];")
@@ -967,12 +977,12 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         emit_staged_acc_zero(o, la, lb, lc, ld)
     if kbd or sacc:
         o("    int fdv = -1;  // first function of d (valid once a step with this d ran)")
-    # With dg.rot the walk over the c range starts at step (task mod length)
+    # With bit 0 of dg.rot the walk over the c range starts at step (task mod length)
     # and wraps around, so that tasks sharing a bra shell a do not flush the
     # same K'_ac elements at the same time; the steps and their sums are the
     # same in either order.
     o("    const int n_st = c_hi - c_lo + 1;")
-    o("    const int rot0 = dg.rot ? task % n_st : 0;")
+    o("    const int rot0 = (dg.rot & 1) ? task % n_st : 0;")
     o("    for (int st = 0; st < n_st; ++st) {")
     o("      int s_i = st + rot0;")
     o("      if (s_i >= n_st) s_i -= n_st;")

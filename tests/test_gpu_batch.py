@@ -121,7 +121,7 @@ def test_autotune_keeps_results(ragged, torch_cuda):
     assert [p["cls"] for p in plan] == [p["cls"] for p in before]
     for p in plan:
         assert p["cl"] >= 1 and p["grid"] in (0, 2048) and p["tasks"] > 0 and p["ms"] > 0
-        assert p["acc"] in (-1, 0, 1, 2) and p["rot"] in (0, 1)
+        assert p["acc"] in (-1, 0, 1, 2) and p["rot"] in (0, 1, 2, 3)
     J, K0, K1 = _batch_jk(torch, gb, Ps, As)
     for i in range(len(ws)):
         assert rel_err(J[i], J0[i]) < 1e-13

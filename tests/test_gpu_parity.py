@@ -168,6 +168,23 @@ def test_concurrent_classes_equal_serialized(spd_case, torch_cuda):
         assert np.array_equal(K1[m], K0[m]), m
 
 
+def test_xcd_task_deal_bitwise(spd_case, torch_cuda):
+    """Dealing the task list to the XCDs in contiguous eighths (task order
+    flag 2) changes which workgroup runs a task, not what a task sums, so
+    with exact fixed-point accumulation J and K are bitwise unchanged; the
+    grid caps (one wave per task, 2048 waves, ragged task counts) exercise
+    the padding of the deal."""
+    torch = torch_cuda
+    w, ob, gb, P = spd_case
+    J0, K0 = _jk_gpu(torch, gb, [P], [1])
+    base = gb.plan()
+    for grid in (0, 2048, 13):
+        gb.set_plan([dict(p, rot=2, grid=grid) for p in base])
+        J1, K1 = _jk_gpu(torch, gb, [P], [1])
+        assert np.array_equal(J1[0], J0[0]) and np.array_equal(K1[0], K0[0]), grid
+    gb.set_plan(base)
+
+
 def test_tiles_span_rows_and_ragged_tail(torch_cuda):
     """12 atoms of 2s1p: rows of up to 5 tiles of 64 with ragged ends."""
     torch = torch_cuda
