@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (default plan only)")
+    ap.add_argument("--kick", type=float, default=1e-4, help="c5/c5l: delta-kick strength along z (a.u.)")
     ap.add_argument("--serialize", action="store_true",
                     help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
                          "kernel-trace profiler so that each kernel's duration is its own")
@@ -233,7 +234,7 @@ def _c5_state(a, torch, cq, inputs, natom):
     Sh = res.S @ X
     Po = Sh @ res.P @ Sh
     lam, U = np.linalg.eigh(X @ Dz @ X)
-    Uk = (U * np.exp(-1j * 1e-4 * lam)) @ U.T
+    Uk = (U * np.exp(-1j * a.kick * lam)) @ U.T
     P0 = Uk @ Po @ Uk.conj().T
     d = lambda m: torch.from_numpy(np.ascontiguousarray(m)).cuda()
     return gb, res, (d(res.h), d(X), d(Dz), d(P0))
@@ -346,7 +347,7 @@ def bench_c5l(a, torch, cq, inputs):
         "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (MLP f32)", "data": "synthetic",
         "config": {"workload": f"RT-TDSCF learned midpoint: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, "
-                               f"{natom // 2} doubly occupied; kick 1e-4 along z; dt 0.05; {nall} steps, network "
+                               f"{natom // 2} doubly occupied; kick {a.kick:g} along z; dt 0.05; {nall} steps, network "
                                f"trained on the first {nt}; first-iterate acceptance {acc:g} for plain, learned "
                                f"and ablation; MMUT restart every {a.mmut_restart} steps", "nbf": gb.nbf,
                    "dipole_reference": ref_name},
@@ -375,7 +376,7 @@ def bench_c5(a, torch, cq, inputs):
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"RT-TDSCF: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, {natom // 2} doubly occupied; "
-                               f"kick 1e-4 a.u. along z, dt 0.05 a.u.; EM2", "nbf": gb.nbf,
+                               f"kick {a.kick:g} a.u. along z, dt 0.05 a.u.; EM2", "nbf": gb.nbf,
                    "quartets_per_build": counts},
         "builds_per_step": builds, "s_per_build": dt / builds,
         "quartets_per_s": counts * builds / dt, "scf_energy": res.energy, "dipole_last": float(mu[-1]),
