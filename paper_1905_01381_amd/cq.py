@@ -258,6 +258,19 @@ class Basis:
                         "ms": float(ms[k])})
         return out
 
+    def save_plan(self, path: str) -> None:
+        """Write the current plan records (e.g. after autotune) as JSON."""
+        import json
+        with open(path, "w") as f:
+            json.dump([dict(p, cls=list(p["cls"])) for p in self.plan()], f, indent=1)
+
+    def load_plan(self, path: str) -> None:
+        """Apply plan records written by save_plan (same molecules)."""
+        import json
+        with open(path) as f:
+            recs = json.load(f)
+        self.set_plan([dict(p, cls=tuple(p["cls"])) for p in recs])
+
     def set_plan(self, plan: list) -> None:
         """Apply plan records (as returned by ``plan``) to their classes."""
         rec = np.zeros(10 * max(len(plan), 1), np.int32)
