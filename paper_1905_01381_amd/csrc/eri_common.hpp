@@ -145,9 +145,10 @@ struct MolInfo {
     int s0, ns;       // first shell, shells
 };
 
-// Work of one class (la lb|lc ld): one task per (molecule, a, 8 consecutive
-// b, 8 consecutive d, a range of c); the wave loops over c.  Lane 8 i + j
-// holds the quartet (a b_i | c d_j).  Shells of each angular momentum are
+// Work of one class (la lb|lc ld): one task per (molecule, a, R consecutive
+// b, 64/R consecutive d, a range of c), R the class's tile rows (8 unless the
+// generator says otherwise); the wave loops over c.  Lane (64/R) i + j holds
+// the quartet (a b_i | c d_j).  Shells of each angular momentum are
 // listed molecule by molecule in index order (shl_*); ppos maps an oriented
 // shell pair (higher l first; a >= b for equal l) of one molecule to its
 // position in its pair class.
@@ -170,21 +171,37 @@ struct TaskMap {
     const unsigned long long* masks;
 };
 
-// Sums over the 8 lanes sharing i (lanes 8i..8i+7) / sharing j.
-__device__ __forceinline__ double red_j(double v)
+// Sums over the C lanes of a tile row (lanes C i .. C i + C - 1) / over the
+// 64 / C lanes of a tile column (lane = C i + j).
+template <int C>
+__device__ __forceinline__ double red_cols(double v)
 {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+#pragma unroll
+    for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ __forceinline__ double red_i(double v)
+template <int C>
+__device__ __forceinline__ double red_rows(double v)
 {
-    v += __shfl_xor(v, 8, 64);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
+#pragma unroll
+    for (int o = C; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+template <int C>
+__device__ __forceinline__ float red_colsf(float v)
+{
+#pragma unroll
+    for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int C>
+__device__ __forceinline__ float red_rowsf(float v)
+{
+#pragma unroll
+    for (int o = C; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 
 // Densities and outputs of one build, interleaved [mu][nu][slot] within each
 // molecule's block.
@@ -306,20 +323,6 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-__device__ __forceinline__ float red_jf(float v)
-{
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    return v;
-}
-__device__ __forceinline__ float red_if(float v)
-{
-    v += __shfl_xor(v, 8, 64);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
 
 __device__ __forceinline__ double wave_sum(double v)
 {

@@ -52,8 +52,32 @@ def lit(x) -> str:
     return v + "f" if PREC["T"] == "float" else v
 
 
+# Task tile of the kernel being emitted: ROWS bra shells b by COLS = 64 / ROWS
+# ket shells d, lane = COLS * i + j.
+TILE = {"rows": 8}
+
+
+def set_tile(rows: int) -> None:
+    TILE["rows"] = rows
+
+
+def rows_() -> int:
+    return TILE["rows"]
+
+
+def cols_() -> int:
+    return 64 // TILE["rows"]
+
+
 def red(name: str) -> str:
-    return name + ("f" if PREC["T"] == "float" else "")
+    """Lane sums: red_j over the COLS lanes of a row, red_i over the ROWS
+    lanes of a column."""
+    f = "f" if PREC["T"] == "float" else ""
+    if name == "red_j":
+        return f"red_cols{f}<{cols_()}>"
+    if name == "red_i":
+        return f"red_rows{f}<{cols_()}>"
+    return name + f
 
 
 def cvx(expr: str) -> str:
@@ -358,7 +382,7 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
         for j in range(nb):
             s = " + ".join(f"{V(i, j, k, l)} * xcd{k}{l}" for k in range(nc) for l in range(nd))
             out(f"    {{ const {T_()} s = {red('red_j')}({lit(2)} * ({s}));")
-            out(f"      if (dg.acc_lvl) {{ if (dj == 0) s_jab[(js * {na * nb} + {i * nb + j}) * 8 + bi] += s; }}")
+            out(f"      if (dg.acc_lvl) {{ if (dj == 0) s_jab[(js * {na * nb} + {i * nb + j}) * {rows_()} + bi] += s; }}")
             out(f"      else if (dj == 0 && rowv) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     for k in range(nc):
         for l in range(nd):
@@ -386,7 +410,7 @@ def emit_digest(out: Emitter, la, lb, lc, ld):
         for l in range(nd):
             s = " + ".join(f"{V(i, j, k, l)} * xbc{j}{k}" for j in range(nb) for k in range(nc))
             out(f"    {{ const {T_()} s = {red('red_i')}({s});")
-            out(f"      if (dg.acc_lvl) {{ if (bi == 0) s_kad[(ks * {na * nd} + {i * nd + l}) * 8 + dj] += s; }}")
+            out(f"      if (dg.acc_lvl) {{ if (bi == 0) s_kad[(ks * {na * nd} + {i * nd + l}) * {cols_()} + dj] += s; }}")
             out(f"      else if (bi == 0 && colv) acc_k(mc, kidx(dg, mc, fa + {i}, fd + {l}, ks), s); }}")
     for j in range(nb):
         for k in range(nc):
@@ -830,10 +854,27 @@ def acc_doubles(la, lb, lc, ld):
     return 0 if is_staged(la, lb, lc, ld) else 64 * ncart(lb) * ncart(ld)
 
 
+# Rows of the task tile per unstaged class (default 8: 8 b x 8 d).  Fewer
+# rows (R b x 64/R d) flush fewer K'_bc lanes per step (R nb nc nK) and more
+# J'_cd lanes (64/R nc nd nJ).  Measured on the 40-atom two-component build
+# (nK = 8, nJ = 1), every class tried was slower with fewer rows: (dp|ps)
+# 77.6 -> 84.4 ms and (dp|ds) 89.1 -> 96.4 ms at R = 2, (ps|ps) 30.6 -> 32.6
+# and (ds|ps) 52.7 -> 55.3 ms at R = 4, (ds|ds) 35.2 -> 37.9 ms at R = 2; so
+# every class keeps R = 8.
+TILE_ROWS = {}
+
+
+def tile_rows(la, lb, lc, ld):
+    if is_staged(la, lb, lc, ld):
+        return 8
+    return TILE_ROWS.get((la, lb, lc, ld), 8)
+
+
 def acc8_doubles(la, lb, lc, ld):
     """LDS doubles per density slot for the task accumulators of J'_ab (one
     per wave row) and K'_ad (one per wave column); unstaged classes only."""
-    return 0 if is_staged(la, lb, lc, ld) else 8 * (ncart(la) * ncart(lb) + ncart(la) * ncart(ld))
+    r = tile_rows(la, lb, lc, ld)
+    return 0 if is_staged(la, lb, lc, ld) else r * ncart(la) * ncart(lb) + (64 // r) * ncart(la) * ncart(ld)
 
 
 def emit_acc_zero(o: Emitter, la, lb, lc, ld):
@@ -844,8 +885,8 @@ def emit_acc_zero(o: Emitter, la, lb, lc, ld):
     o("    if (dg.acc_lvl >= 2)")
     o(f"      for (int t = 0; t < {kbd} * dg.nK; ++t) s_kbd[t * 64 + lane] = 0.0;")
     o("    if (dg.acc_lvl) {")
-    o(f"      if (dj == 0) for (int t = 0; t < {nab} * dg.nJ; ++t) s_jab[t * 8 + bi] = 0.0;")
-    o(f"      if (bi == 0) for (int t = 0; t < {nad} * dg.nK; ++t) s_kad[t * 8 + dj] = 0.0;")
+    o(f"      if (dj == 0) for (int t = 0; t < {nab} * dg.nJ; ++t) s_jab[t * {rows_()} + bi] = 0.0;")
+    o(f"      if (bi == 0) for (int t = 0; t < {nad} * dg.nK; ++t) s_kad[t * {cols_()} + dj] = 0.0;")
     o("    }")
 
 
@@ -858,13 +899,13 @@ def emit_acc_flush(o: Emitter, la, lb, ld):
     o("        if (js >= 0 && dj == 0 && rowv) {")
     for i in range(na):
         for j in range(nb):
-            o(f"          {{ const double s = s_jab[(js * {na * nb} + {i * nb + j}) * 8 + bi];")
+            o(f"          {{ const double s = s_jab[(js * {na * nb} + {i * nb + j}) * {rows_()} + bi];")
             o(f"            if (s != 0.0) acc_j(mc, jidx(dg, mc, fa + {i}, fb + {j}, js), s); }}")
     o("        }")
     o("        if (ks >= 0 && bi == 0 && fdv >= 0) {")
     for i in range(na):
         for l in range(nd):
-            o(f"          {{ const double s = s_kad[(ks * {na * nd} + {i * nd + l}) * 8 + dj];")
+            o(f"          {{ const double s = s_kad[(ks * {na * nd} + {i * nd + l}) * {cols_()} + dj];")
             o(f"            if (s != 0.0) acc_k(mc, kidx(dg, mc, fa + {i}, fdv + {l}, ks), s); }}")
     o("        }")
     o("      }")
@@ -891,6 +932,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     staged = is_staged(la, lb, lc, ld)
     nv = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
     set_prec(prec)
+    set_tile(tile_rows(la, lb, lc, ld))
     body = Emitter("    ")
     dig = Emitter("    ")
     if staged:
@@ -925,9 +967,9 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("  extern __shared__ double s_acc[];")
         o(f"  double* const s_kbd = s_acc;")
         o(f"  double* const s_jab = s_acc + (dg.acc_lvl >= 2 ? {kbd} * dg.nK : 0);")
-        o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * 8} * dg.nJ;")
+        o(f"  double* const s_kad = s_jab + {ncart(la) * ncart(lb) * rows_()} * dg.nJ;")
     o("  const int lane = threadIdx.x;")
-    o("  const int bi = lane >> 3, dj = lane & 7;")
+    o(f"  const int bi = lane >> {cols_().bit_length() - 1}, dj = lane & {cols_() - 1};")
     sacc = staged_acc_doubles(la, lb, lc, ld)
     if staged:
         # per-wave region: the integral stage, then the task accumulators
@@ -1105,8 +1147,9 @@ def gen(lmax: int) -> dict:
     # dispatch tables
     o("typedef void (*eri_jk_fn)(PairSet, PairSet, TaskMap, Digest, const double*);")
     o("// jks / jk32s: the kernels of the exchanged orientation (lc ld|la lb), or NULL; acc_s / acc8_s their")
-    o("// LDS accumulator sizes; sacc: stage-region task accumulator doubles per lane and density slot")
-    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; int acc8; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); eri_jk_fn jks; eri_jk_fn jk32s; int acc_s, acc8_s; int sacc; };")
+    o("// LDS accumulator sizes; sacc: stage-region task accumulator doubles per lane and density slot;")
+    o("// rows / rows_s: bra shells per task tile (64 / rows ket shells) of each orientation")
+    o("struct EriClassEntry { int la, lb, lc, ld; int nv; int stage; int acc; int acc8; eri_jk_fn jk; eri_jk_fn jk32; void (*blk)(PairSet, PairSet, const int*, int, double*, const double*); eri_jk_fn jks; eri_jk_fn jk32s; int acc_s, acc8_s; int sacc; int rows, rows_s; };")
     o(f"static const int kNumEriClasses = {len(classes)};")
     o("static const EriClassEntry kEriClasses[] = {")
     for (la, lb, lc, ld) in classes:
@@ -1115,9 +1158,11 @@ def gen(lmax: int) -> dict:
         if (la, lb, lc, ld) in swapped:
             sn = class_name(lc, ld, la, lb)
             sw = f"eri_jk_{sn}, eri_jk32_{sn}, {acc_doubles(lc, ld, la, lb)}, {acc8_doubles(lc, ld, la, lb)}"
+            rs = tile_rows(lc, ld, la, lb)
         else:
             sw = "nullptr, nullptr, 0, 0"
-        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, {acc8_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}, {sw}, {staged_acc_doubles(la, lb, lc, ld)}}},")
+            rs = 8
+        o(f"  {{{la}, {lb}, {lc}, {ld}, {nv}, {stage_sizes[(la, lb, lc, ld)]}, {acc_doubles(la, lb, lc, ld)}, {acc8_doubles(la, lb, lc, ld)}, eri_jk_{cn}, eri_jk32_{cn}, eri_block_{cn}, {sw}, {staged_acc_doubles(la, lb, lc, ld)}, {tile_rows(la, lb, lc, ld)}, {rs}}},")
     o("};")
     for cn, nv, nvrr in stats:
         print(f"{cn}: nv={nv} vrr_nodes={nvrr}", file=sys.stderr)
