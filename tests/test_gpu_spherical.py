@@ -167,3 +167,31 @@ def test_spherical_rhf_against_oracle(torch_cuda):
     res = scf.scf(gb, w.mol, "RS", 1, conv=1e-11)
     assert res.converged
     assert abs((res.energy - res.e_nuc) - ref) < 1e-8
+
+
+def test_spherical_em2_steps_against_oracle(torch_cuda):
+    """Real-time EM2 steps on a spherical, generally contracted basis (2
+    atoms, nbf 28) from the RHF ground state after a kick, against the
+    oracle's EM2 in the same basis."""
+    torch = torch_cuda
+    from oracle import rt
+    from paper_1905_01381_amd import cq
+    w = inputs.small(2, inputs.SHELLS_3S2P1D, seed=41, lo=0.3, hi=50.0, spherical=True, general=True)
+    ob = osph.SphericalBasis.from_molecule(w.mol)
+    gb = cq.Basis.from_molecule(w.mol)
+    P, h, S, X, E = oscf.rhf(ob, w.mol, 1)
+    Sh = S @ X
+    Po = (Sh @ P @ Sh).astype(complex)
+    Dz = ob.one_electron("dipole", direction=2)
+    U = rt.expm_herm(X @ Dz @ X, 1e-2)
+    P0 = U @ Po @ U.conj().T
+    r = cq.RT(gb, _dev(torch, h), _dev(torch, X), _dev(torch, Dz), _dev(torch, P0), 0.05, cq.RT_EM2)
+    _, mu, nb = r.step(3)
+    Pg = r.density().cpu().numpy()
+    Pr = P0
+    for _ in range(3):
+        Pr = rt.em2_step(ob, h, X, Pr, 0.05)
+    assert list(nb) == [2, 2, 2]
+    assert np.abs(Pg - Pr).max() < 1e-10 * np.abs(Pr).max()
+    _, mu_ref = rt.energy_dipole(ob, h, X, Dz, Pr)
+    assert abs(mu[-1] - mu_ref) < 1e-10
