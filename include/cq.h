@@ -20,10 +20,11 @@
  *   alias inputs.
  * - Functions are ordered shell by shell in the order given to
  *   cq_basis_create; within a shell, Cartesian components are lexicographic
- *   (l=1: x y z; l=2: xx xy xz yy yz zz), each normalized to unit self-overlap.
- *   Bases made by cq_basis_create_general may also hold spherical d shells
- *   and generally contracted shells (see there); nbf then counts the
- *   caller's functions.
+ *   (l=1: x y z; l=2: xx xy xz yy yz zz; l=3: xxx xxy xxz xyy xyz xzz yyy
+ *   yyz yzz zzz), each normalized to unit self-overlap.  Bases made by
+ *   cq_basis_create_general may also hold spherical d and f shells and
+ *   generally contracted shells (see there); nbf then counts the caller's
+ *   functions.
  * - Work is enqueued on the given stream (NULL = the default stream) and is
  *   asynchronous unless stated.  A handle must not be used from two streams
  *   at the same time.
@@ -45,7 +46,7 @@ typedef enum {
     CQ_EINVAL = 1,        /* invalid argument */
     CQ_ENOMEM = 2,        /* device or host allocation failed */
     CQ_EHIP = 3,          /* a HIP runtime call failed */
-    CQ_EUNSUPPORTED = 4,  /* angular momentum above d, or a feature not built */
+    CQ_EUNSUPPORTED = 4,  /* angular momentum above f, or a feature not built */
     CQ_ENONFINITE = 5,    /* a non-finite value was found in an input density */
     CQ_ENOTCONV = 6       /* an iterative step did not converge */
 } cq_status;
@@ -89,7 +90,10 @@ const char* cq_last_error(void);
 /* Create a basis from host arrays (copied; the caller keeps ownership).
  *   nshell          number of shells (>= 1)
  *   xyz[nshell*3]   shell centers (bohr)
- *   l[nshell]       angular momentum, 0..2
+ *   l[nshell]       angular momentum, 0..3 (classes with an f shell run one
+ *                   workgroup per shell quartet with its recurrences in LDS;
+ *                   CQ_EUNSUPPORTED if the device's LDS per workgroup cannot
+ *                   hold one ket component of a class)
  *   nprim[nshell]   primitives per shell, 1..8
  *   alpha[], coef[] exponents and raw contraction coefficients, concatenated
  *                   shell by shell (sum(nprim) entries)
@@ -138,13 +142,16 @@ cq_status cq_basis_create_batch(int nmol, const int* nshell_mol, const double* x
  * normalized as in cq_basis_create.  A spherical d shell has 5 functions,
  * the unit-normalized real solid harmonics m = -2..2: xy, yz,
  * (3z^2 - r^2), xz, (x^2 - y^2) (each as a combination of the normalized
- * Cartesian xx..zz of the same contraction).  Every matrix of the handle
- * (densities, J, K, one-electron integrals, cq_fock2e_2c's spin blocks, the
- * real-time matrices) is in these functions; internally the integrals run
- * over Cartesian segmented shells and densities pass through the d-shell
- * transformation on the way in, results on the way out.  Shell-level
- * outputs (cq_schwarz, cq_eri_quartet, cq_basis_nshell) refer to the
- * expanded Cartesian segmented shells.  l = 3 and above: CQ_EUNSUPPORTED.
+ * Cartesian xx..zz of the same contraction); a spherical f shell has 7,
+ * m = -3..3: y(3x^2 - y^2), xyz, y(4z^2 - x^2 - y^2), z(2z^2 - 3x^2 - 3y^2),
+ * x(4z^2 - x^2 - y^2), z(x^2 - y^2), x(x^2 - 3y^2).  Every matrix of the
+ * handle (densities, J, K, one-electron integrals, cq_fock2e_2c's spin
+ * blocks, the real-time matrices) is in these functions; internally the
+ * integrals run over Cartesian segmented shells and densities pass through
+ * the shell transformations on the way in, results on the way out.
+ * Shell-level outputs (cq_schwarz, cq_eri_quartet, cq_basis_nshell) refer
+ * to the expanded Cartesian segmented shells.  l = 4 and above:
+ * CQ_EUNSUPPORTED.
  * Allocates and synchronizes like cq_basis_create. */
 cq_status cq_basis_create_general(int nmol, const int* nshell_mol, const double* xyz, const int* l,
                                   const int* nprim, const int* ncontr, const int* pure, const double* alpha,

@@ -75,7 +75,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     extra = extra or []
     os.makedirs(OBJ, exist_ok=True)
     srcs = generate(verbose) + [os.path.join(CSRC, "cq_api.hip"), os.path.join(CSRC, "one_electron.hip"),
-                                 os.path.join(CSRC, "rt.hip")]
+                                 os.path.join(CSRC, "rt.hip"), os.path.join(CSRC, "eri_hl.hip")]
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     objs, logs = [], []
     with cf.ThreadPoolExecutor(jobs) as ex:

@@ -357,9 +357,9 @@ class Basis:
     def quartet_counts(self) -> dict:
         """{(la, lb, lc, ld): unique shell quartets of an unscreened build}."""
         n = ctypes.c_int()
-        cls = (ctypes.c_int * 256)()
-        cnt = (ctypes.c_longlong * 64)()
-        _check(lib().cq_quartet_counts(self.h, 64, cls, cnt, ctypes.byref(n)))
+        cls = (ctypes.c_int * 512)()
+        cnt = (ctypes.c_longlong * 128)()
+        _check(lib().cq_quartet_counts(self.h, 128, cls, cnt, ctypes.byref(n)))
         return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
 
     def sync_status(self, stream=None) -> int:

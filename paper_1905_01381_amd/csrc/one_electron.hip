@@ -53,8 +53,8 @@ __global__ void one_electron_kernel(OneEArgs g, const double* __restrict__ boys_
     const double A[3] = {g.xyz[3 * sa], g.xyz[3 * sa + 1], g.xyz[3 * sa + 2]};
     const double B[3] = {g.xyz[3 * sb], g.xyz[3 * sb + 1], g.xyz[3 * sb + 2]};
     const int na = (la + 1) * (la + 2) / 2, nb = (lb + 1) * (lb + 2) / 2;
-    double out[36];
-    for (int k = 0; k < 36; ++k) out[k] = 0.0;
+    double out[100];  // shells up to f
+    for (int k = 0; k < 100; ++k) out[k] = 0.0;
     const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
     for (int pa = 0; pa < g.nprim[sa]; ++pa)
         for (int pb = 0; pb < g.nprim[sb]; ++pb) {
@@ -108,13 +108,13 @@ __global__ void one_electron_kernel(OneEArgs g, const double* __restrict__ boys_
                     const double C[3] = {g.cxyz[3 * c], g.cxyz[3 * c + 1], g.cxyz[3 * c + 2]};
                     const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
                     const double T = p * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-                    double F[5];
-                    boys_fp64<4>(T, boys_tab, F);
-                    // V[e][m]: e over all components of degree 0..L (<= 35), m <= L
-                    double V[35][5];
+                    double F[7];
+                    boys_fp64<6>(T, boys_tab, F);
+                    // V[e][m]: e over all components of degree 0..L (<= 84), m <= L
+                    double V[84][7];
                     const double base = 2 * 3.14159265358979323846 / p * Kab;
                     for (int m = 0; m <= L; ++m) V[0][m] = base * F[m];
-                    int off[6] = {0, 1, 4, 10, 20, 35};
+                    const int off[8] = {0, 1, 4, 10, 20, 35, 56, 84};
                     for (int le = 1; le <= L; ++le)
                         for (int ci = 0; ci < (le + 1) * (le + 2) / 2; ++ci) {
                             int e[3];

@@ -77,7 +77,7 @@ class Molecule:
         return int(n)
 
     def as_spherical(self) -> "Molecule":
-        """The same shells with every d shell spherical."""
+        """The same shells with every d and f shell spherical."""
         pure = (np.asarray(self.shell_l) >= 2).astype(np.int32)
         nco = self.ncontr if self.ncontr is not None else np.ones(self.nshell, np.int32)
         return Molecule(self.atoms, self.charges, self.shell_atom, self.shell_l, self.shell_xyz, self.nprim,
@@ -135,7 +135,7 @@ def general_molecule(natom: int, ls: list[int], lo: float, hi: float, rng: np.ra
                      spherical: bool = True, charge: float = 1.0) -> Molecule:
     """The recipe's atoms with the n_l shells of each l merged into one
     generally contracted shell (n_l contractions over min(3 n_l, 8)
-    exponents); d shells spherical if ``spherical``."""
+    exponents); d and f shells spherical if ``spherical``."""
     atoms = lattice_geometry(natom, rng)
     counts = {l: ls.count(l) for l in sorted(set(ls))}
     per_atom = []
@@ -176,6 +176,9 @@ def random_orbitals(nbf: int, nocc: int, rng: np.random.Generator, complex_: boo
 # --------------------------------------------------------------------------
 SHELLS_2S1P = [0, 0, 1]
 SHELLS_3S2P1D = [0, 0, 0, 1, 1, 2]
+# a triple-zeta-like polarized atom with one f shell (35 Cartesian / 30
+# spherical functions per atom), for the classes above d
+SHELLS_4S3P2D1F = [0, 0, 0, 0, 1, 1, 1, 2, 2, 3]
 
 
 @dataclass
@@ -247,8 +250,8 @@ def small(natom: int, ls: list[int], seed: int = 0, nocc: int | None = None,
           lo: float = 0.1, hi: float = 1.0e3, complex_: bool = False, spherical: bool = False,
           general: bool = False) -> Workload:
     """A reduced molecule with the same recipe (for parity at oracle-sized
-    inputs); ``spherical``: d shells spherical; ``general``: the general
-    contraction variant."""
+    inputs); ``spherical``: d and f shells spherical; ``general``: the
+    general contraction variant."""
     rng = np.random.default_rng(seed)
     if general:
         mol = general_molecule(natom, ls, lo, hi, rng, spherical=spherical)

@@ -82,7 +82,7 @@ def test_thresholds_flags():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcq.so not built")
 def test_general_basis_argument_errors():
-    """cq_basis_create_general refuses l = 3 (CQ_EUNSUPPORTED) and ncontr or
+    """cq_basis_create_general refuses l = 4 (CQ_EUNSUPPORTED) and ncontr or
     pure outside their ranges (CQ_EINVAL) before touching the device."""
     import numpy as np
     from paper_1905_01381_amd import cq, inputs
@@ -101,8 +101,8 @@ def test_general_basis_argument_errors():
         return L.cq_basis_create_general(1, nsm.ctypes.data_as(ip), xyz.ctypes.data_as(dp), ls.ctypes.data_as(ip),
                                          npr.ctypes.data_as(ip), nco.ctypes.data_as(ip), pure.ctypes.data_as(ip),
                                          a.ctypes.data_as(dp), c.ctypes.data_as(dp), None, ctypes.byref(h))
-    assert create([0, 1, 3], [1, 1, 1], [0, 0, 1]) == cq.CQ_EUNSUPPORTED
-    assert b"l=3" in L.cq_last_error()
+    assert create([0, 1, 4], [1, 1, 1], [0, 0, 1]) == cq.CQ_EUNSUPPORTED
+    assert b"l=4" in L.cq_last_error()
     assert create([0, 1, 2], [1, 0, 1], [0, 0, 1]) == cq.CQ_EINVAL
     assert create([0, 1, 2], [1, 65, 1], [0, 0, 1]) == cq.CQ_EINVAL
     assert create([0, 1, 2], [1, 1, 1], [0, 0, 2]) == cq.CQ_EINVAL
@@ -120,3 +120,7 @@ def test_general_recipe_counts():
     assert list(m.shell_l) == [0, 1, 2] * 2
     assert list(m.ncontr) == [3, 2, 1] * 2 and list(m.nprim) == [8, 6, 3] * 2
     assert m.nbf == 28 and m.coef.size == 2 * (24 + 12 + 3)
+    f = inputs.small(2, inputs.SHELLS_4S3P2D1F, spherical=True, general=True).mol
+    assert list(f.shell_l) == [0, 1, 2, 3] * 2 and list(f.ncontr) == [4, 3, 2, 1] * 2
+    assert f.nbf == 2 * (4 + 9 + 10 + 7)
+    assert inputs.small(2, inputs.SHELLS_4S3P2D1F).mol.nbf == 2 * 35

@@ -114,3 +114,37 @@ def test_nuclear_matrix_by_quadrature():
             ref -= z * _contract(mol, B, prim, mu, nu)
         assert abs(V[mu, nu] - ref) < 1e-11 * scale, (mu, nu, V[mu, nu], ref)
     assert np.allclose(V, V.T, atol=1e-14 * scale)
+
+
+def test_f_shell_one_electron_by_quadrature():
+    """Sampled elements with an f shell (f-s, f-p, f-d, f-f on two centres)
+    of the overlap, kinetic, dipole and nuclear-attraction matrices."""
+    rng = np.random.default_rng(21)
+    mol = inputs.make_molecule(2, [0, 1, 2, 3], 0.3, 20.0, rng)
+    B = oracle.Basis.from_molecule(mol)
+    fs = _functions(mol)
+    by_l = {}
+    for mu, (s, _) in enumerate(fs):
+        by_l.setdefault(int(mol.shell_l[s]), []).append(mu)
+    picks = [(by_l[3][rng.integers(len(by_l[3]))], by_l[lb][rng.integers(len(by_l[lb]))]) for lb in (0, 1, 2, 3)]
+    picks.append((by_l[3][3], by_l[3][17]))  # f components on different atoms
+    org = np.array([0.4, -0.7, 0.2])
+    Z = np.array([1.0, 2.5])
+    C = np.array([mol.shell_xyz[0], [0.3, 0.9, -0.4]])
+    mats = {"overlap": (B.overlap(), quad.overlap_prim),
+            "kinetic": (B.one_electron("kinetic"), quad.kinetic_prim),
+            "dipole": (B.one_electron("dipole", direction=1, origin=org),
+                       lambda ea, a, A, eb, b, Bc: quad.dipole_prim(ea, a, A, eb, b, Bc, org, 1))}
+    for name, (M, prim) in mats.items():
+        scale = np.abs(M).max()
+        for mu, nu in picks:
+            ref = _contract(mol, B, prim, mu, nu)
+            assert abs(M[mu, nu] - ref) < 1e-12 * scale, (name, mu, nu, M[mu, nu], ref)
+    V = B.one_electron("nuclear", charges=Z, centers=C)
+    scale = np.abs(V).max()
+    for mu, nu in picks:
+        ref = 0.0
+        for z, c in zip(Z, C):
+            prim = lambda ea, a, A, eb, b, Bc, c=c: quad.nuclear_prim(ea, a, A, eb, b, Bc, c)
+            ref -= z * _contract(mol, B, prim, mu, nu)
+        assert abs(V[mu, nu] - ref) < 1e-11 * scale, (mu, nu, V[mu, nu], ref)

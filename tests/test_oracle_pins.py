@@ -92,7 +92,8 @@ def _random_quartet_case(rng, ls):
 
 
 @pytest.mark.parametrize("ls", [(1, 0, 0, 0), (0, 0, 1, 0), (1, 1, 0, 0), (1, 0, 1, 0), (2, 0, 0, 0),
-                                (2, 1, 1, 0), (1, 1, 1, 1), (2, 0, 2, 0), (2, 2, 1, 1), (2, 2, 2, 2)])
+                                (2, 1, 1, 0), (1, 1, 1, 1), (2, 0, 2, 0), (2, 2, 1, 1), (2, 2, 2, 2),
+                                (3, 0, 0, 0), (3, 1, 2, 0), (3, 2, 3, 1), (3, 3, 3, 3)])
 def test_eri_prim_brute_quadrature(ls):
     rng = np.random.default_rng(sum(ls) * 7 + ls[0])
     for _ in range(2):
@@ -112,8 +113,9 @@ def _tiny(ls=(0, 1, 2), natom=2, seed=1):
     return inputs.make_molecule(natom, list(ls), 0.3, 20.0, rng)
 
 
-def test_contracted_functions_unit_norm_by_quadrature():
-    mol = _tiny()
+@pytest.mark.parametrize("ls", [(0, 1, 2), (0, 1, 2, 3)])
+def test_contracted_functions_unit_norm_by_quadrature(ls):
+    mol = _tiny(ls=ls)
     B = oracle.Basis.from_molecule(mol)
     coef, cnorm = B.normalized_coefs()
     po = np.concatenate([[0], np.cumsum(mol.nprim)])
@@ -183,6 +185,29 @@ def test_contracted_shell_block_by_quadrature():
         fn = [B.offsets[s] + i for s, i in zip(sh, idx)]
         tot *= np.prod([cnorm[f] for f in fn])
         assert blk[tuple(idx)] == pytest.approx(tot, rel=1e-9, abs=1e-12)
+
+
+def test_contracted_f_shell_blocks_by_quadrature():
+    """Sampled elements of contracted blocks with f shells ((fd|ps), (ff|fp))
+    by brute-force quadrature over primitives."""
+    mol = _tiny(ls=(0, 1, 2, 3), natom=2, seed=9)
+    B = oracle.Basis.from_molecule(mol)
+    coef, cnorm = B.normalized_coefs()
+    po = np.concatenate([[0], np.cumsum(mol.nprim)])
+    rng = np.random.default_rng(2)
+    for sh in ([3, 6, 5, 0], [3, 7, 7, 1]):  # f(0) d(1) p(1) s(0); f(0) f(1) f(1) p(0)
+        blk = B.eri_shell(*sh)
+        comps = [quad.cart_components(int(mol.shell_l[s])) for s in sh]
+        for _ in range(2):
+            idx = [rng.integers(0, len(c)) for c in comps]
+            tot = 0.0
+            for ps in itertools.product(*[range(po[s], po[s + 1]) for s in sh]):
+                cc = np.prod([coef[i] for i in ps])
+                tot += cc * quad.eri_prim(*sum(([comps[k][idx[k]], mol.alpha[ps[k]], mol.shell_xyz[sh[k]]]
+                                                for k in range(4)), []))
+            fn = [B.offsets[s] + i for s, i in zip(sh, idx)]
+            tot *= np.prod([cnorm[f] for f in fn])
+            assert blk[tuple(idx)] == pytest.approx(tot, rel=1e-9, abs=1e-12 * np.abs(blk).max()), (sh, idx)
 
 
 # ---------------------------------------------------------------- J / K

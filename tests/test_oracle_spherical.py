@@ -57,13 +57,30 @@ def test_low_orders_are_the_textbook_functions():
         ratio(p, q)
 
 
-def _general_molecule(seed=3):
-    """Two atoms: a generally contracted spherical d (two contractions over
-    three exponents) and a segmented spherical d on atom 0; s, p and a
-    Cartesian d on atom 1."""
+def test_f_orders_are_the_textbook_functions():
+    """l = 3, m = -3..3: y(3x^2 - y^2), xyz, y(4z^2 - x^2 - y^2),
+    z(2z^2 - 3x^2 - 3y^2), x(4z^2 - x^2 - y^2), z(x^2 - y^2), x(x^2 - 3y^2)
+    (each up to a positive factor)."""
+    expect = [{(2, 1, 0): 3, (0, 3, 0): -1}, {(1, 1, 1): 1}, {(0, 1, 2): 4, (2, 1, 0): -1, (0, 3, 0): -1},
+              {(0, 0, 3): 2, (2, 0, 1): -3, (0, 2, 1): -3}, {(1, 0, 2): 4, (3, 0, 0): -1, (1, 2, 0): -1},
+              {(2, 0, 1): 1, (0, 2, 1): -1}, {(3, 0, 0): 1, (1, 2, 0): -3}]
+    for p, q in zip(sph.solid_harmonics(3), expect):
+        k = next(iter(q))
+        r = p[k] / q[k]
+        assert r > 0 and p.keys() == q.keys()
+        assert all(abs(p[e] - r * q[e]) < 1e-12 for e in q)
+
+
+_SHELLS_D = [(0, 2, 2, 1), (0, 2, 1, 1), (1, 0, 1, 0), (1, 1, 2, 0), (1, 2, 1, 0)]  # atom, l, ncontr, pure
+_SHELLS_F = [(0, 3, 2, 1), (0, 3, 1, 0), (1, 2, 1, 1), (1, 1, 1, 0), (1, 3, 1, 1)]
+
+
+def _general_molecule(seed=3, shells=_SHELLS_D):
+    """Two atoms: by default a generally contracted spherical d (two
+    contractions over three exponents) and a segmented spherical d on atom
+    0; s, p and a Cartesian d on atom 1."""
     rng = np.random.default_rng(seed)
     xyz = np.array([[0.0, 0.0, 0.0], [0.3, -0.4, 1.5]])
-    shells = [(0, 2, 2, 1), (0, 2, 1, 1), (1, 0, 1, 0), (1, 1, 2, 0), (1, 2, 1, 0)]  # atom, l, ncontr, pure
     sx, sl, npr, nco, pu, al, co = [], [], [], [], [], [], []
     for at, l, nc, p in shells:
         sx.append(xyz[at])
@@ -123,6 +140,23 @@ def test_spherical_and_general_overlap_by_quadrature():
         assert S[i, j] == pytest.approx(ref, abs=2e-13), (i, j)
 
 
+def test_spherical_f_overlap_by_quadrature():
+    """As above with f shells: a generally contracted spherical f (two
+    contractions), a Cartesian f, a spherical d, a p and a second spherical
+    f on the other atom."""
+    g = _general_molecule(seed=5, shells=_SHELLS_F)
+    B = sph.SphericalBasis(**g)
+    S = B.overlap()
+    funcs = _explicit_functions(g)
+    assert len(funcs) == B.nbf == 7 * 2 + 10 + 5 + 3 + 7
+    norms = np.array([np.sqrt(_quad_overlap(f, f)) for f in funcs])
+    for i, j in itertools.product(range(B.nbf), repeat=2):
+        if j < i:
+            continue
+        ref = _quad_overlap(funcs[i], funcs[j]) / (norms[i] * norms[j])
+        assert S[i, j] == pytest.approx(ref, abs=2e-13), (i, j)
+
+
 def test_spherical_block_orthonormal_and_free_of_r2():
     """Within one contracted d shell the five spherical functions are
     orthonormal under the oracle's contracted overlap and orthogonal to the
@@ -137,13 +171,14 @@ def test_spherical_block_orthonormal_and_free_of_r2():
     assert np.allclose(T @ Sdd @ r2, 0.0, atol=1e-13)
 
 
-def test_spherical_jk_rotation_invariant_energies():
+@pytest.mark.parametrize("shells", [_SHELLS_D, _SHELLS_F], ids=["d", "f"])
+def test_spherical_jk_rotation_invariant_energies(shells):
     """Rotating the molecule rigidly about the origin leaves Tr(P J[P]) and
     Tr(P K[P]) of the ground-state-like density P = C C^T with C from the
     lowest orbitals of the overlap-orthonormalized core (a function of the
     geometry only) unchanged: a spherical transformation mixing in the wrong
     functions would break the invariance."""
-    g = _general_molecule(seed=7)
+    g = _general_molecule(seed=7, shells=shells)
     def energies(xyz):
         gg = dict(g, shell_xyz=xyz)
         B = sph.SphericalBasis(**gg)
