@@ -73,6 +73,32 @@ __device__ __forceinline__ void exps(int l, int ci, int e[3]) { gexps(hl_cum(l) 
 
 __device__ __forceinline__ int gdeg(int g) { return s_comp[g] >> 12; }
 
+// Exponent pairs of the bra components ab and of one chunk's ket components
+// (c | d << 12, each x | y << 4 | z << 8), filled per workgroup / chunk.
+#define HL_NPAIR 100
+__shared__ int s_ab[HL_NPAIR];
+__shared__ int s_cd[HL_NPAIR];
+
+__device__ __forceinline__ int pack3(const int e[3]) { return e[0] | (e[1] << 4) | (e[2] << 8); }
+__device__ __forceinline__ void unpack3(int v, int e[3])
+{
+    e[0] = v & 15;
+    e[1] = (v >> 4) & 15;
+    e[2] = (v >> 8) & 15;
+}
+
+// s_tab[k] for k < n: components (k / n2 of degree l1, k % n2 of degree l2), pair index offset k0
+__device__ void fill_pairs(int* tab, int l1, int l2, int k0, int n)
+{
+    const int n2 = hl_nc(l2);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        int a[3], b[3];
+        exps(l1, (k0 + k) / n2, a);
+        exps(l2, (k0 + k) % n2, b);
+        tab[k] = pack3(a) | (pack3(b) << 12);
+    }
+}
+
 __device__ __forceinline__ int gidx(int x, int y, int z) { return hl_cum(x + y + z) + cidx(y, z); }
 
 __device__ __forceinline__ int first_dir(const int e[3]) { return e[0] > 0 ? 0 : (e[1] > 0 ? 1 : 2); }
@@ -136,12 +162,11 @@ __device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int c
 {
     const double* EC = s + L.oEC;
     double* ECD = s + L.oECD;
-    const int nd = hl_nc(L.ld);
     for (int x = threadIdx.x; x < L.ne * cdn; x += blockDim.x) {
-        const int eg = x / cdn, r = x % cdn, cd = cd0 + r;
+        const int eg = x / cdn, r = x - eg * cdn;
         int c[3], d[3];
-        exps(L.lc, cd / nd, c);
-        exps(L.ld, cd % nd, d);
+        unpack3(s_cd[r], c);
+        unpack3(s_cd[r] >> 12, d);
         const int le = gdeg(eg);
         const int mx = c[0] + d[0], my = c[1] + d[1], mz = c[2] + d[2];
         double t = 0.0;
@@ -166,8 +191,8 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
     double* EC = s + L.oEC;
     double* ECD = s + L.oECD;
     double* OUT = s + L.oOUT;
-    const int nb = hl_nc(L.lb);
     for (int x = tid; x < L.nab * cdn; x += nth) OUT[x] = 0.0;
+    fill_pairs(s_cd, L.lc, L.ld, cd0, cdn);
     const double AB[3] = {a.bra.ABx[p], a.bra.ABy[p], a.bra.ABz[p]};
     const double CD[3] = {a.ket.ABx[q], a.ket.ABy[q], a.ket.ABz[q]};
     for (int kp = 0; kp < a.bra.nprim2; ++kp) {
@@ -229,30 +254,40 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
             }
             ket_transfer(L, s, 0, cd0, cdn);
             for (int f = 1; f <= L.Fk; ++f) {
+                // one (e, f component) per thread, all its orders m in turn
+                // (orders are contiguous in every level)
                 const int nfc = hl_nc(f), nm = L.Fk - f + 1;
-                const int n = L.ne * nfc * nm;
-                for (int x = tid; x < n; x += nth) {
-                    const int m = x % nm, r = x / nm;
-                    const int fc = r % nfc, eg = r / nfc;
+                for (int r = tid; r < L.ne * nfc; r += nth) {
+                    const int eg = r / nfc, fc = r - eg * nfc;
                     int fe[3], e[3];
                     exps(f, fc, fe);
                     const int le = gexps(eg, e);
                     const int i = first_dir(fe);
                     fe[i] -= 1;
                     const int f1 = cidx(fe[1], fe[2]);
-                    double v = WQ[i] * lev(s, L, f - 1, le, eg, f1, m + 1);
-                    if (fe[i] > 0) {
-                        const int k = fe[i];
+                    const double* A1 = s + (f == 1 ? t0i(L, le, eg, 0) : levi(L, f - 1, eg, f1, 0));
+                    const int k2 = fe[i];
+                    const double* A2 = A1;
+                    if (k2 > 0) {
                         fe[i] -= 1;
                         const int f2 = cidx(fe[1], fe[2]);
-                        v += k * (oo2q * lev(s, L, f - 2, le, eg, f2, m) - rq2 * lev(s, L, f - 2, le, eg, f2, m + 1));
+                        A2 = s + (f == 2 ? t0i(L, le, eg, 0) : levi(L, f - 2, eg, f2, 0));
                     }
-                    if (e[i] > 0) {
-                        const int k = e[i];
+                    const int k3 = e[i];
+                    const double* A3 = A1;
+                    if (k3 > 0) {
                         e[i] -= 1;
-                        v += k * oo2pq * lev(s, L, f - 1, le - 1, gidx(e[0], e[1], e[2]), f1, m + 1);
+                        const int eg1 = gidx(e[0], e[1], e[2]);
+                        A3 = s + (f == 1 ? t0i(L, le - 1, eg1, 0) : levi(L, f - 1, eg1, f1, 0));
                     }
-                    s[levi(L, f, eg, fc, m)] = v;
+                    double* dst = s + levi(L, f, eg, fc, 0);
+                    const double c2 = k2 * oo2q, d2 = k2 * rq2, c3 = k3 * oo2pq;
+                    for (int m = 0; m < nm; ++m) {
+                        double v = WQ[i] * A1[m + 1];
+                        if (k2 > 0) v += c2 * A2[m] - d2 * A2[m + 1];
+                        if (k3 > 0) v += c3 * A3[m + 1];
+                        dst[m] = v;
+                    }
                 }
                 __syncthreads();
                 ket_transfer(L, s, f, cd0, cdn);
@@ -261,10 +296,10 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
         __syncthreads();  // ECD complete
         // bra transfer: OUT[ab, r] += sum_e E^{ab}_e [e|cd)
         for (int x = tid; x < L.nab * cdn; x += nth) {
-            const int ab = x / cdn, r = x % cdn;
+            const int ab = x / cdn, r = x - ab * cdn;
             int ea[3], eb[3];
-            exps(L.la, ab / nb, ea);
-            exps(L.lb, ab % nb, eb);
+            unpack3(s_ab[ab], ea);
+            unpack3(s_ab[ab] >> 12, eb);
             double t = 0.0;
             for (int ex = 0; ex <= ea[0] + eb[0]; ++ex) {
                 const double wx = ecoef(EA, L.la, L.lb, 0, ea[0], eb[0], ex);
@@ -378,6 +413,7 @@ __global__ __launch_bounds__(HL_THREADS_MAX) void eri_hl_kernel(HlArgs a)
     const int t = blockIdx.x;
     if (t >= a.ntask) return;
     fill_comps();
+    fill_pairs(s_ab, L.la, L.lb, 0, L.nab);  // visible after the first barrier of a chunk
     const int4 tk = a.tasks[t];
     const int p = tk.x;
     if (a.out) {

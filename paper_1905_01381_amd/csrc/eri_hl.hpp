@@ -5,7 +5,7 @@
 
 #define HL_LMAX 3            // highest shell angular momentum of this path
 #define HL_THREADS_MAX 1024  // threads of one workgroup, at most
-#define HL_LDS_STATIC 1024   // bytes of static LDS the kernel keeps besides the layout
+#define HL_LDS_STATIC 2048   // bytes of static LDS the kernel keeps besides the layout
 
 // threads per workgroup for a class: wide workgroups for the large classes
 // (their recurrence levels hold thousands of entries), one wave for the
