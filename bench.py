@@ -62,13 +62,13 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l", "f"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (default plan only)")
     ap.add_argument("--kick", type=float, default=1e-4, help="c5/c5l: delta-kick strength along z (a.u.)")
     ap.add_argument("--serialize", action="store_true",
                     help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
                          "kernel-trace profiler so that each kernel's duration is its own")
-    ap.add_argument("--atoms", type=int, default=0, help="c3/c5: atoms (0 = the full workload)")
+    ap.add_argument("--atoms", type=int, default=0, help="c3/c5/f: atoms (0 = the full workload; f: 6)")
     ap.add_argument("--nmol", type=int, default=16, help="c4: number of molecules (smallest first)")
     ap.add_argument("--rt-steps", type=int, default=2000, help="c5l: trajectory length")
     ap.add_argument("--rt-train", type=int, default=500, help="c5l: steps recorded for training")
@@ -355,6 +355,39 @@ def bench_c5l(a, torch, cq, inputs):
     }
 
 
+def bench_f(a, torch, cq, inputs):
+    """Shells up to f: one J and one K per build of a real density on atoms
+    of the 4s3p2d1f recipe (exponents 0.1..1e3).  Reports builds/s and,
+    from a pass with per-class timing, the time of the classes with an f
+    shell (workgroup-per-quartet kernel) against the generated classes."""
+    natom = a.atoms or 6
+    w = inputs.small(natom, inputs.SHELLS_4S3P2D1F, seed=1, lo=0.1, hi=1.0e3)
+    gb = cq.Basis.from_molecule(w.mol)
+    S = gb.one_electron("overlap").cpu().numpy()
+    P = torch.from_numpy(np.ascontiguousarray(_ortho_density(S, w.orbitals))).cuda()
+    qc = gb.quartet_counts()
+    nq = sum(qc.values())
+    nq_f = sum(v for k, v in qc.items() if 3 in k)
+    _log(f"f: {natom} atoms, nbf {gb.nbf}, {nq:.4e} unique quartets, {nq_f:.4e} with an f shell")
+    sec = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
+    gb.profile(True, reset=True)
+    gb.jk([P])
+    torch.cuda.synchronize()
+    prof = gb.profile_read()
+    gb.profile(False)
+    t_f = sum(v[0] for k, v in prof.items() if 3 in k)
+    t_all = sum(v[0] for v in prof.values())
+    top = sorted(((k, v[0]) for k, v in prof.items() if 3 in k), key=lambda kv: -kv[1])[:5]
+    return {"metric": "J+K builds/sec, shells up to f", "value": 1.0 / sec, "unit": "builds/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"shells up to f: {natom} atoms 4s3p2d1f (3 primitives), nbf {gb.nbf}, "
+                                   "one real density", "nbf": gb.nbf, "quartets": nq, "quartets_f": nq_f},
+            "serialized_ms": {"f_classes": t_f, "other_classes": t_all - t_f},
+            "f_quartets_per_s": nq_f / (t_f / 1e3), "other_quartets_per_s": (nq - nq_f) / ((t_all - t_f) / 1e3),
+            "slowest_f_classes_ms": {"".join("spdf"[x] for x in k): ms for k, ms in top}}
+
+
 def bench_c5(a, torch, cq, inputs):
     """EM2 real-time steps on the Z=1 lattice workload after an RHF ground
     state and a delta kick along z."""
@@ -448,7 +481,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if a.workload != "c2":
-        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5l": bench_c5l}[a.workload]
+        fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5l": bench_c5l, "f": bench_f}[a.workload]
         print(json.dumps(fn(a, torch, cq, inputs)), flush=True)
         return
     w, gb, P2 = build_inputs(torch, cq, inputs)

@@ -151,33 +151,38 @@ __device__ void etable(double* tab, int lu, int lv, const double PA[3], const do
     }
 }
 
-__device__ __forceinline__ double ecoef(const double* tab, int lu, int lv, int k, int u, int v, int e)
-{
-    return tab[((k * (lu + 1) + u) * (lv + 1) + v) * (lu + lv + 1) + e];
-}
-
 // Ket transfer of level f (values at order 0) into the chunk's [e|cd):
-// ECD[eg cdn + r] += sum over f components of E^{cd}_f [e|f].
+// ECD[eg cdn + r] += sum over f components of E^{cd}_f [e|f].  Index
+// arithmetic is hoisted: per entry the three per-axis coefficient rows and
+// the level row of e, per f_x the component offset of the (f_y, f_z) block.
 __device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int cdn)
 {
     const double* EC = s + L.oEC;
     double* ECD = s + L.oECD;
+    const int ne1 = L.Fk + 1, stride_v = ne1, stride_u = (L.ld + 1) * ne1, stride_k = (L.lc + 1) * stride_u;
+    const int nfc = hl_nc(f), nm = L.Fk - f + 1;
     for (int x = threadIdx.x; x < L.ne * cdn; x += blockDim.x) {
         const int eg = x / cdn, r = x - eg * cdn;
         int c[3], d[3];
         unpack3(s_cd[r], c);
         unpack3(s_cd[r] >> 12, d);
-        const int le = gdeg(eg);
+        const double* ex = EC + c[0] * stride_u + d[0] * stride_v;
+        const double* ey = EC + stride_k + c[1] * stride_u + d[1] * stride_v;
+        const double* ez = EC + 2 * stride_k + c[2] * stride_u + d[2] * stride_v;
+        // level f row of e: component fc at row[fc * nm] (order 0)
+        const double* row = f == 0 ? s + t0i(L, gdeg(eg), eg, 0) : s + L.oS[f % 3] + eg * nfc * nm;
         const int mx = c[0] + d[0], my = c[1] + d[1], mz = c[2] + d[2];
         double t = 0.0;
-        for (int fx = 0; fx <= (mx < f ? mx : f); ++fx)
-            for (int fy = 0; fy <= (my < f - fx ? my : f - fx); ++fy) {
-                const int fz = f - fx - fy;
-                if (fz > mz) continue;
-                const double w = ecoef(EC, L.lc, L.ld, 0, c[0], d[0], fx) * ecoef(EC, L.lc, L.ld, 1, c[1], d[1], fy) *
-                                 ecoef(EC, L.lc, L.ld, 2, c[2], d[2], fz);
-                t += w * lev(s, L, f, le, eg, cidx(fy, fz), 0);
+        for (int fx = 0; fx <= (mx < f ? mx : f); ++fx) {
+            const int sy = f - fx;              // f_y + f_z
+            const int cb = sy * (sy + 1) / 2;   // first component with this f_y + f_z
+            const double wx = ex[fx];
+            const int fy0 = sy - mz > 0 ? sy - mz : 0, fy1 = my < sy ? my : sy;
+            for (int fy = fy0; fy <= fy1; ++fy) {
+                const int fz = sy - fy;
+                t += wx * ey[fy] * ez[fz] * row[(cb + fz) * nm];
             }
+        }
         ECD[x] += t;
     }
 }
@@ -295,18 +300,25 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
         }
         __syncthreads();  // ECD complete
         // bra transfer: OUT[ab, r] += sum_e E^{ab}_e [e|cd)
+        const int ne1 = L.Eb + 1, stride_u = (L.lb + 1) * ne1, stride_k = (L.la + 1) * stride_u;
         for (int x = tid; x < L.nab * cdn; x += nth) {
             const int ab = x / cdn, r = x - ab * cdn;
             int ea[3], eb[3];
             unpack3(s_ab[ab], ea);
             unpack3(s_ab[ab] >> 12, eb);
+            const double* wxr = EA + ea[0] * stride_u + eb[0] * ne1;
+            const double* wyr = EA + stride_k + ea[1] * stride_u + eb[1] * ne1;
+            const double* wzr = EA + 2 * stride_k + ea[2] * stride_u + eb[2] * ne1;
+            const double* col = ECD + r;
             double t = 0.0;
             for (int ex = 0; ex <= ea[0] + eb[0]; ++ex) {
-                const double wx = ecoef(EA, L.la, L.lb, 0, ea[0], eb[0], ex);
+                const double wx = wxr[ex];
                 for (int ey = 0; ey <= ea[1] + eb[1]; ++ey) {
-                    const double wy = wx * ecoef(EA, L.la, L.lb, 1, ea[1], eb[1], ey);
+                    const double wy = wx * wyr[ey];
+                    // components with e_x = ex, e_y = ey in order of e_z: global
+                    // index cum(ex + ey + ez) + cidx(ey, ez)
                     for (int ez = 0; ez <= ea[2] + eb[2]; ++ez)
-                        t += wy * ecoef(EA, L.la, L.lb, 2, ea[2], eb[2], ez) * ECD[gidx(ex, ey, ez) * cdn + r];
+                        t += wy * wzr[ez] * col[gidx(ex, ey, ez) * cdn];
                 }
             }
             OUT[x] += t;

@@ -60,7 +60,7 @@ def traffic(fetch_db: str, write_db: str, copy_mib: float) -> str:
     per = collections.defaultdict(lambda: [0.0, 0.0, 0.0, 0.0, 0, 0])
     for p, cn, i in ((f, "FETCH_SIZE", 0), (w, "WRITE_SIZE", 1)):
         for k, du, cnt in p.values():
-            if not k.startswith("eri_jk") or cn not in cnt:
+            if not k.startswith("eri_") or cn not in cnt:
                 continue
             per[k][i] += cnt[cn][0]
             per[k][4 + i] += 1
@@ -85,7 +85,7 @@ def valu(db: str) -> str:
     per = collections.defaultdict(lambda: collections.defaultdict(float))
     n = collections.Counter()
     for k, du, cnt in p.values():
-        if not k.startswith("eri_jk"):
+        if not k.startswith("eri_"):
             continue
         n[k] += 1
         per[k]["ms"] += du / 1e6
