@@ -116,6 +116,26 @@ __device__ __forceinline__ double ipow(double x, int n)
     return r;
 }
 
+// The workgroup walks n1 x n2 entries (i1 slow, i2 fast).  With n2 <= the
+// group size, thread t keeps i2 = t mod n2 and steps i1 by group / n2 (one
+// division per walk instead of one per entry); otherwise entries are dealt
+// in flat order.  Either way a given entry always falls to the same thread.
+template <class F>
+__device__ __forceinline__ void for_pairs(int n1, int n2, F&& body)
+{
+    const int nth = blockDim.x, tid = threadIdx.x;
+    if (n2 <= nth) {
+        const int groups = nth / n2, i2 = tid % n2, g = tid / n2;
+        if (g < groups)
+            for (int i1 = g; i1 < n1; i1 += groups) body(i1, i2);
+    } else {
+        for (int x = tid; x < n1 * n2; x += nth) {
+            const int i1 = x / n2;
+            body(i1, x - i1 * n2);
+        }
+    }
+}
+
 // bra table entry (degree l, global index g, order m)
 __device__ __forceinline__ int t0i(const HlLayout& L, int l, int g, int m)
 {
@@ -161,8 +181,7 @@ __device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int c
     double* ECD = s + L.oECD;
     const int ne1 = L.Fk + 1, stride_v = ne1, stride_u = (L.ld + 1) * ne1, stride_k = (L.lc + 1) * stride_u;
     const int nfc = hl_nc(f), nm = L.Fk - f + 1;
-    for (int x = threadIdx.x; x < L.ne * cdn; x += blockDim.x) {
-        const int eg = x / cdn, r = x - eg * cdn;
+    for_pairs(L.ne, cdn, [&](int eg, int r) {
         int c[3], d[3];
         unpack3(s_cd[r], c);
         unpack3(s_cd[r] >> 12, d);
@@ -183,8 +202,8 @@ __device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int c
                 t += wx * ey[fy] * ez[fz] * row[(cb + fz) * nm];
             }
         }
-        ECD[x] += t;
-    }
+        ECD[eg * cdn + r] += t;
+    });
 }
 
 // One chunk of ket components [cd0, cd0 + cdn) of the quartet (bra pair p,
@@ -262,8 +281,7 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
                 // one (e, f component) per thread, all its orders m in turn
                 // (orders are contiguous in every level)
                 const int nfc = hl_nc(f), nm = L.Fk - f + 1;
-                for (int r = tid; r < L.ne * nfc; r += nth) {
-                    const int eg = r / nfc, fc = r - eg * nfc;
+                for_pairs(L.ne, nfc, [&](int eg, int fc) {
                     int fe[3], e[3];
                     exps(f, fc, fe);
                     const int le = gexps(eg, e);
@@ -293,7 +311,7 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
                         if (k3 > 0) v += c3 * A3[m + 1];
                         dst[m] = v;
                     }
-                }
+                });
                 __syncthreads();
                 ket_transfer(L, s, f, cd0, cdn);
             }
@@ -301,8 +319,7 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
         __syncthreads();  // ECD complete
         // bra transfer: OUT[ab, r] += sum_e E^{ab}_e [e|cd)
         const int ne1 = L.Eb + 1, stride_u = (L.lb + 1) * ne1, stride_k = (L.la + 1) * stride_u;
-        for (int x = tid; x < L.nab * cdn; x += nth) {
-            const int ab = x / cdn, r = x - ab * cdn;
+        for_pairs(L.nab, cdn, [&](int ab, int r) {
             int ea[3], eb[3];
             unpack3(s_ab[ab], ea);
             unpack3(s_ab[ab] >> 12, eb);
@@ -321,8 +338,8 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
                         t += wy * wzr[ez] * col[gidx(ex, ey, ez) * cdn];
                 }
             }
-            OUT[x] += t;
-        }
+            OUT[ab * cdn + r] += t;
+        });
     }
     __syncthreads();
 }
