@@ -70,6 +70,8 @@ def parse():
                          "kernel-trace profiler so that each kernel's duration is its own")
     ap.add_argument("--atoms", type=int, default=0, help="c3/c5/f: atoms (0 = the full workload; f: 6)")
     ap.add_argument("--nmol", type=int, default=16, help="c4: number of molecules (smallest first)")
+    ap.add_argument("--c4-variants", default="batched,single",
+                    help="c4: comma list of batched (one handle) and single (one handle per molecule)")
     ap.add_argument("--rt-steps", type=int, default=2000, help="c5l: trajectory length")
     ap.add_argument("--rt-train", type=int, default=500, help="c5l: steps recorded for training")
     ap.add_argument("--epochs", type=int, default=200, help="c5l: training epochs")
@@ -91,6 +93,17 @@ def kernel_source_hash(cls: str) -> str:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def _clean(x):
+    """NaN (a variant that was not run) -> None, so that the line stays JSON."""
+    if isinstance(x, float) and x != x:
+        return None
+    if isinstance(x, dict):
+        return {k: _clean(v) for k, v in x.items()}
+    if isinstance(x, list):
+        return [_clean(v) for v in x]
+    return x
 
 
 def _log(msg):
@@ -178,9 +191,12 @@ def bench_c4(a, torch, cq, inputs):
     counts = sum(gb.quartet_counts().values())
     _log(f"c4: {len(ws)} molecules ({min(sizes[pick])}..{max(sizes[pick])} atoms), nbf {gb.mol_nbf[0]}.."
          f"{gb.mol_nbf[-1]}, {counts:.3e} quartets")
-    t_default = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
+    variants = a.c4_variants.split(",")
+    long_run = counts > 1e11  # builds of minutes: a progress line per class
+    gb.trace(long_run)
+    t_default = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup) if "batched" in variants else float("nan")
     _log(f"c4 batched default plan: {t_default:.3f} s/build")
-    if a.no_tune:
+    if a.no_tune or "batched" not in variants:
         # cq_autotune times every candidate on the whole batch: about 30
         # launches per class, too long for batches of minutes per build
         plan, t_tune, t_tuned = gb.plan(), 0.0, t_default
@@ -190,16 +206,23 @@ def bench_c4(a, torch, cq, inputs):
         t_tune = time.perf_counter() - t0
         t_tuned = _timed(torch, lambda: gb.jk([P]), a.steps, a.warmup)
         _log(f"c4 batched tuned plan: {t_tuned:.3f} s/build (autotune {t_tune:.1f} s)")
-    singles = [cq.Basis.from_molecule(w.mol) for w in ws]
+    t_single = float("nan")
+    if "single" in variants:
+        singles = [cq.Basis.from_molecule(w.mol) for w in ws]
+        for g1 in singles:
+            g1.trace(long_run)
 
-    def per_mol():
-        for g1, p in zip(singles, Ps):
-            g1.jk([p])
-    t_single = _timed(torch, per_mol, a.steps, a.warmup)
-    _log(f"c4 one handle per molecule: {t_single:.3f} s/build")
+        def per_mol():
+            for g1, p in zip(singles, Ps):
+                g1.jk([p])
+        t_single = _timed(torch, per_mol, a.steps, a.warmup)
+        _log(f"c4 one handle per molecule: {t_single:.3f} s/build")
+    if "batched" not in variants:
+        t_tuned = t_single
     return {
-        "metric": "J+K builds/sec, batched uneven launch (all molecules per class launch, "
-                  + ("default plan)" if a.no_tune else "autotuned)"),
+        "metric": ("J+K builds/sec, batched uneven launch (all molecules per class launch, "
+                   + ("default plan)" if a.no_tune else "autotuned)")) if "batched" in variants
+                  else "J+K builds/sec, one handle per molecule",
         "value": 1.0 / t_tuned, "unit": "builds/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": t_tuned * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
@@ -482,7 +505,7 @@ def main():
     torch.cuda.set_device(0)
     if a.workload != "c2":
         fn = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c5l": bench_c5l, "f": bench_f}[a.workload]
-        print(json.dumps(fn(a, torch, cq, inputs)), flush=True)
+        print(json.dumps(_clean(fn(a, torch, cq, inputs))), flush=True)
         return
     w, gb, P2 = build_inputs(torch, cq, inputs)
     G = torch.empty_like(P2)
