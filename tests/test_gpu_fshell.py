@@ -14,6 +14,8 @@ the generated kernels, in one build.
   unscreened result; at 1e-6 the counters add up to the unique quartets and
   the change stays within the skipped quartets' bounds.
 * Builds repeat bitwise; the allocation-free entry point matches.
+* Routed mode, the autotuner, per-class timing, the RS driver and real-time
+  EM2 steps on bases with f shells.
 """
 import itertools
 import sys
@@ -267,3 +269,73 @@ def test_f_classes_profiled(fcase, torch_cuda):
     print(f"f classes timed: {len(fcls)}, total {sum(v[0] for v in fcls.values()):.3f} ms", flush=True)
     assert set(fcls) == {k for k, n in gb.quartet_counts().items() if 3 in k and n > 0}
     assert all(v[1] == 1 and v[0] > 0 for v in fcls.values())
+
+
+def test_f_routed_mode(fcase, torch_cuda):
+    """Routed mode on a basis with f shells: the f classes stay FP64, the
+    counters add up to the unique quartets, and the energy stays within
+    1e-6 Eh of the oracle at FP32 below 1e-5."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w, ob, gb, P = fcase
+    total = sum(gb.quartet_counts().values())
+    nq_f = sum(v for k, v in gb.quartet_counts().items() if 3 in k)
+    r = gb.jk([_dev(torch, P)], th=cq.thresholds(mode=1, fp32_below=1e-5))
+    st = gb.build_stats()
+    assert st["fp64"] + st["fp32"] + st["skipped"] == total
+    assert st["fp64"] >= nq_f
+    Jr, Kr = ob.jk(P)
+    J, K = r.J[0].cpu().numpy(), r.K[0].cpu().numpy()
+    dE = abs((2 * np.sum(P * J) - np.sum(P * K)) - (2 * np.sum(P * Jr) - np.sum(P * Kr)))
+    print(f"routed: {st}, dE {dE:.2e}", flush=True)
+    assert dE < 1e-6
+
+
+def test_f_autotune_keeps_results(torch_cuda):
+    """cq_autotune on a basis with f shells tunes the generated classes and
+    leaves the build's results unchanged (the f classes have no plan)."""
+    torch = torch_cuda
+    from paper_1905_01381_amd import cq
+    w = inputs.small(2, SHELLS, seed=19, lo=0.3, hi=50.0)
+    ob = oracle.Basis.from_molecule(w.mol)
+    P = oracle.density_real(ob.overlap(), w.orbitals)
+    gb = cq.Basis.from_molecule(w.mol)
+    r0 = gb.jk([_dev(torch, P)])
+    J0, K0 = r0.J[0].cpu().numpy(), r0.K[0].cpu().numpy()
+    plan = gb.autotune(nmat=1, reps=1)
+    assert plan and all(3 not in p["cls"] for p in plan)
+    r1 = gb.jk([_dev(torch, P)])
+    assert rel_err(r1.J[0].cpu().numpy(), J0) < 1e-13 and rel_err(r1.K[0].cpu().numpy(), K0) < 1e-13
+    Jr, Kr = ob.jk(P)
+    assert rel_err(r1.J[0].cpu().numpy(), Jr) < TOL_JK and rel_err(r1.K[0].cpu().numpy(), Kr) < TOL_JK
+
+
+def test_f_rhf_and_em2_against_oracle(torch_cuda):
+    """The RS driver and real-time EM2 steps on a basis with f shells (2
+    atoms of charge 1, s p d f each, nbf 40) against the oracle's RHF and
+    EM2."""
+    torch = torch_cuda
+    from oracle import rt
+    from oracle import scf as oscf
+    from paper_1905_01381_amd import cq, scf
+    w = inputs.small(2, SHELLS, seed=23, lo=0.3, hi=50.0)
+    ob = oracle.Basis.from_molecule(w.mol)
+    gb = cq.Basis.from_molecule(w.mol)
+    P, h, S, X, E = oscf.rhf(ob, w.mol, 1)
+    res = scf.scf(gb, w.mol, "RS", 1, conv=1e-11)
+    assert res.converged
+    assert abs((res.energy - res.e_nuc) - E) < 1e-8
+    Sh = S @ X
+    Po = (Sh @ P @ Sh).astype(complex)
+    Dz = ob.one_electron("dipole", direction=2)
+    U = rt.expm_herm(X @ Dz @ X, 1e-2)
+    P0 = U @ Po @ U.conj().T
+    r = cq.RT(gb, _dev(torch, h), _dev(torch, X), _dev(torch, Dz), _dev(torch, P0), 0.05, cq.RT_EM2)
+    _, mu, nb = r.step(3)
+    Pg = r.density().cpu().numpy()
+    Pr = P0
+    for _ in range(3):
+        Pr = rt.em2_step(ob, h, X, Pr, 0.05)
+    assert np.abs(Pg - Pr).max() < 1e-10 * np.abs(Pr).max()
+    _, mu_ref = rt.energy_dipole(ob, h, X, Dz, Pr)
+    assert abs(mu[-1] - mu_ref) < 1e-10
