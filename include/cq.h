@@ -274,7 +274,9 @@ cq_status cq_one_electron(cq_basis b, int kind, int dir, const double* origin, i
 
 /* Number of unique contracted shell quartets per class for an unscreened
  * build (bra pair >= ket pair; la>=lb, lc>=ld).  For entry k < maxn:
- * cls[4k..4k+3] = (la, lb, lc, ld), count[k]; *n = number of classes. */
+ * cls[4k..4k+3] = (la, lb, lc, ld), count[k]; *n = number of classes (the
+ * generated s-d classes, then the classes with an f shell that the basis
+ * holds; at most 55). */
 cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, int* n);
 
 /* Quartet counts of the most recent cq_jk_build / cq_fock2e_2c on this
@@ -296,7 +298,8 @@ cq_status cq_build_stats(cq_basis b, unsigned long long* out3, hipStream_t strea
  *      an L2) and
  *      every LDS accumulator level below the highest that fits (less LDS
  *      per wave, more resident waves, more flushes);
- * and keeps the fastest for every later build on the handle.  Every plan is
+ * and keeps the fastest for every later build on the handle.  Classes with
+ * an f shell have one fixed launch form and are not tuned.  Every plan is
  * deterministic; two plans agree to rounding only (the FP64 partial sums a
  * wave forms before its exact fixed-point additions depend on the plan).
  * Synchronizes `stream`; overwrites the handle's work buffers only. */
@@ -328,8 +331,8 @@ cq_status cq_plan_set(cq_basis b, int n, const int* rec);
  * caller's stream; with timing on they run one after another on the
  * caller's stream, so each time is one kernel's own.
  * cq_profile_read synchronizes on the recorded events and returns, per class
- * that ran, cls[4k..4k+3], the summed kernel time ms[k] and launch count
- * count[k]; *n = number of such classes. */
+ * that ran (classes with an f shell included), cls[4k..4k+3], the summed
+ * kernel time ms[k] and launch count count[k]; *n = number of such classes. */
 cq_status cq_profile(cq_basis b, int enable);
 
 /* Progress trace (tracing aid): with enable != 0, every build on this handle
