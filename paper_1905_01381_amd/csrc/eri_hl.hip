@@ -88,7 +88,7 @@ __device__ __forceinline__ void unpack3(int v, int e[3])
 }
 
 // s_tab[k] for k < n: components (k / n2 of degree l1, k % n2 of degree l2), pair index offset k0
-__device__ void fill_pairs(int* tab, int l1, int l2, int k0, int n)
+__device__ __forceinline__ void fill_pairs(int* tab, int l1, int l2, int k0, int n)
 {
     const int n2 = hl_nc(l2);
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -156,7 +156,7 @@ __device__ __forceinline__ double lev(const double* s, const HlLayout& L, int g,
 
 // Per-axis coefficients E_e of (x-P)^e in (x-A)^u (x-B)^v, u <= lu, v <= lv,
 // e <= lu + lv: tab[((k (lu+1) + u) (lv+1) + v) (lu+lv+1) + e], axis k.
-__device__ void etable(double* tab, int lu, int lv, const double PA[3], const double PB[3])
+__device__ __forceinline__ void etable(double* tab, int lu, int lv, const double PA[3], const double PB[3])
 {
     const int ne = lu + lv + 1, n = 3 * (lu + 1) * (lv + 1) * ne;
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
@@ -175,7 +175,7 @@ __device__ void etable(double* tab, int lu, int lv, const double PA[3], const do
 // ECD[eg cdn + r] += sum over f components of E^{cd}_f [e|f].  Index
 // arithmetic is hoisted: per entry the three per-axis coefficient rows and
 // the level row of e, per f_x the component offset of the (f_y, f_z) block.
-__device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int cdn)
+__device__ __forceinline__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int cdn)
 {
     const double* EC = s + L.oEC;
     double* ECD = s + L.oECD;
@@ -208,7 +208,7 @@ __device__ void ket_transfer(const HlLayout& L, double* s, int f, int cd0, int c
 
 // One chunk of ket components [cd0, cd0 + cdn) of the quartet (bra pair p,
 // ket pair q), summed over primitive quartets into OUT[ab cdn + r].
-__device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0, int cdn, double* s)
+__device__ __forceinline__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0, int cdn, double* s)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     double* EA = s + L.oEA;
@@ -349,7 +349,7 @@ __device__ void chunk(const HlArgs& a, const HlLayout& L, int p, int q, int cd0,
 //   J'_ab += 2 v X_cd, J'_cd += 2 v X_ab,
 //   K'_ac += v X_bd, K'_ad += v X_bc, K'_bc += v X_ad, K'_bd += v X_ac;
 // each destination's partial sum over the chunk is one fixed-point add.
-__device__ void digest(const HlArgs& a, const HlLayout& L, const MolView& mc, int p, int q, double deg, int cd0,
+__device__ __forceinline__ void digest(const HlArgs& a, const HlLayout& L, const MolView& mc, int p, int q, double deg, int cd0,
                        int cdn, double* s)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -433,12 +433,11 @@ __device__ void digest(const HlArgs& a, const HlLayout& L, const MolView& mc, in
     }
 }
 
-}  // namespace
-
-__global__ __launch_bounds__(HL_THREADS_MAX) void eri_hl_kernel(HlArgs a)
+// The kernel body for one class; L's class-dependent fields are
+// compile-time constants in every instantiation below.
+__device__ __forceinline__ void hl_body(const HlArgs& a, const HlLayout& L)
 {
     extern __shared__ double s[];
-    const HlLayout L = a.lay;
     const int t = blockIdx.x;
     if (t >= a.ntask) return;
     fill_comps();
@@ -482,4 +481,64 @@ __global__ __launch_bounds__(HL_THREADS_MAX) void eri_hl_kernel(HlArgs a)
         if (nrun) atomicAdd(a.dg.counts, nrun);
         if (nskip) atomicAdd(a.dg.counts + 2, nskip);
     }
+}
+
+}  // namespace
+
+// One instantiation per class: the angular momenta fix every size, offset,
+// loop bound and stride of the recurrences at compile time (the runtime
+// index arithmetic of a class-generic kernel dominated its issue slots);
+// only the ket chunking, which depends on the device's LDS, comes from the
+// launch.
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(HL_THREADS_MAX) void eri_hl_t(HlArgs a)
+{
+    HlLayout L = hl_layout(LA, LB, LC, LD, 0);
+    L.ch = a.lay.ch;
+    L.nch = a.lay.nch;
+    L.oOUT = a.lay.oOUT;
+    L.total = a.lay.total;
+    hl_body(a, L);
+}
+
+#define HL_CASE(A, B, C, D) \
+    if (la == A && lb == B && lc == C && ld == D) return eri_hl_t<A, B, C, D>;
+
+hl_kernel_fn hl_kernel_for(int la, int lb, int lc, int ld)
+{
+    HL_CASE(3, 0, 0, 0)
+    HL_CASE(3, 0, 1, 0)
+    HL_CASE(3, 0, 1, 1)
+    HL_CASE(3, 0, 2, 0)
+    HL_CASE(3, 0, 2, 1)
+    HL_CASE(3, 0, 2, 2)
+    HL_CASE(3, 0, 3, 0)
+    HL_CASE(3, 1, 0, 0)
+    HL_CASE(3, 1, 1, 0)
+    HL_CASE(3, 1, 1, 1)
+    HL_CASE(3, 1, 2, 0)
+    HL_CASE(3, 1, 2, 1)
+    HL_CASE(3, 1, 2, 2)
+    HL_CASE(3, 1, 3, 0)
+    HL_CASE(3, 1, 3, 1)
+    HL_CASE(3, 2, 0, 0)
+    HL_CASE(3, 2, 1, 0)
+    HL_CASE(3, 2, 1, 1)
+    HL_CASE(3, 2, 2, 0)
+    HL_CASE(3, 2, 2, 1)
+    HL_CASE(3, 2, 2, 2)
+    HL_CASE(3, 2, 3, 0)
+    HL_CASE(3, 2, 3, 1)
+    HL_CASE(3, 2, 3, 2)
+    HL_CASE(3, 3, 0, 0)
+    HL_CASE(3, 3, 1, 0)
+    HL_CASE(3, 3, 1, 1)
+    HL_CASE(3, 3, 2, 0)
+    HL_CASE(3, 3, 2, 1)
+    HL_CASE(3, 3, 2, 2)
+    HL_CASE(3, 3, 3, 0)
+    HL_CASE(3, 3, 3, 1)
+    HL_CASE(3, 3, 3, 2)
+    HL_CASE(3, 3, 3, 3)
+    return nullptr;
 }

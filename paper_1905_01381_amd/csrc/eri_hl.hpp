@@ -104,4 +104,8 @@ struct HlArgs {
     double* out;
 };
 
-__global__ void eri_hl_kernel(HlArgs a);
+// The kernel of class (la lb|lc ld) (la = 3, the bra pair class at or above
+// the ket's), or NULL for any other class.  Launch with hl_threads(total)
+// threads and total * 8 bytes of dynamic LDS.
+typedef void (*hl_kernel_fn)(HlArgs);
+hl_kernel_fn hl_kernel_for(int la, int lb, int lc, int ld);
