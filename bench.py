@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5l", "f"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (default plan only)")
     ap.add_argument("--kick", type=float, default=1e-4, help="c5/c5l: delta-kick strength along z (a.u.)")
+    ap.add_argument("--dt", type=float, default=0.05, help="c5l: time step (a.u.)")
     ap.add_argument("--serialize", action="store_true",
                     help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
                          "kernel-trace profiler so that each kernel's duration is its own")
@@ -294,7 +295,7 @@ def bench_c5l(a, torch, cq, inputs):
     a reference midpoint trajectory converged to 1e-12."""
     natom = a.atoms or 12
     gb, res, args = _c5_state(a, torch, cq, inputs, natom)
-    dt, nt, nall, acc = 0.05, a.rt_train, a.rt_steps, a.accept_tol
+    dt, nt, nall, acc = a.dt, a.rt_train, a.rt_steps, a.accept_tol
     runs = {}
 
     def plain(mode, label, sc_tol=1e-10, accept=acc, restart=None):
@@ -370,7 +371,7 @@ def bench_c5l(a, torch, cq, inputs):
         "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (MLP f32)", "data": "synthetic",
         "config": {"workload": f"RT-TDSCF learned midpoint: {natom} atoms Z=1, 3s2p1d, nbf {gb.nbf}, "
-                               f"{natom // 2} doubly occupied; kick {a.kick:g} along z; dt 0.05; {nall} steps, network "
+                               f"{natom // 2} doubly occupied; kick {a.kick:g} along z; dt {dt:g}; {nall} steps, network "
                                f"trained on the first {nt}; first-iterate acceptance {acc:g} for plain, learned "
                                f"and ablation; MMUT restart every {a.mmut_restart} steps", "nbf": gb.nbf,
                    "dipole_reference": ref_name},
