@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (default plan only)")
     ap.add_argument("--kick", type=float, default=1e-4, help="c5/c5l: delta-kick strength along z (a.u.)")
     ap.add_argument("--dt", type=float, default=0.05, help="c5l: time step (a.u.)")
+    ap.add_argument("--rt-chunk", type=int, default=50,
+                    help="c5l: steps per progress line (each line adds one uncounted energy build)")
     ap.add_argument("--serialize", action="store_true",
                     help="c2: run every build with per-class timing on (classes one after another), e.g. under a "
                          "kernel-trace profiler so that each kernel's duration is its own")
@@ -304,7 +306,7 @@ def bench_c5l(a, torch, cq, inputs):
         if restart:
             r.set_restart(restart)
         t0 = time.perf_counter()
-        ei, E, mu, nb = _rt_steps(r, nall, label)
+        ei, E, mu, nb = _rt_steps(r, nall, label, a.rt_chunk)
         torch.cuda.synchronize()
         runs[label] = {"E_idx": ei, "E": E, "mu": mu, "nb": nb, "s": time.perf_counter() - t0, "stats": r.stats()}
         r.close()
@@ -314,7 +316,7 @@ def bench_c5l(a, torch, cq, inputs):
         r.set_params(sc_tol=1e-10, max_iter=60, accept_tol=acc)
         r.record(True, 4096, 1)
         t0 = time.perf_counter()
-        e1, E1, mu1, nb1 = _rt_steps(r, nt, label + " (recording)")
+        e1, E1, mu1, nb1 = _rt_steps(r, nt, label + " (recording)", a.rt_chunk)
         r.record(False)
         t1 = time.perf_counter()
         loss = r.train(epochs=0 if zero else a.epochs, lr=3e-3)
@@ -324,7 +326,7 @@ def bench_c5l(a, torch, cq, inputs):
             r.weights(np.zeros(354, np.float32))
         r.set_mode(cq.RT_LEARNED)
         t2 = time.perf_counter()
-        e2, E2, mu2, nb2 = _rt_steps(r, nall - nt, label)
+        e2, E2, mu2, nb2 = _rt_steps(r, nall - nt, label, a.rt_chunk)
         torch.cuda.synchronize()
         runs[label] = {"E_idx": np.concatenate([e1, e2 + nt]), "E": np.concatenate([E1, E2]),
                        "mu": np.concatenate([mu1, mu2]), "nb": np.concatenate([nb1, nb2]),
