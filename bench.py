@@ -553,8 +553,13 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][0])
     cls, (ms_tot, launches) = dom
     avg_s = ms_tot / launches / 1e3
-    fq = flops.per_quartet(*cls, nJ=1, nK=8)
-    achieved = fq * counts[cls] / avg_s / 1e12
+    # algorithmic work: per primitive quartet above the primitive cut, plus
+    # per shell quartet (transfers, digestion)
+    f_prim, f_fixed = flops.parts(*cls, nJ=1, nK=8)
+    nprimq = gb.prim_quartet_counts()[cls]
+    work = f_prim * nprimq + f_fixed * counts[cls]
+    fq = work / counts[cls]
+    achieved = work / avg_s / 1e12
     # HBM bytes per launch of the dominant kernel from the committed counter
     # profile, only while the kernel's source is the one that was profiled
     traffic = None
@@ -598,6 +603,9 @@ def main():
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": traffic,
             "flops_per_quartet": fq,
+            "flops_per_prim_quartet": f_prim,
+            "flops_per_quartet_fixed": f_fixed,
+            "prim_quartets_per_launch": nprimq,
             "quartets_per_launch": counts[cls],
             "avg_launch_ms": avg_s * 1e3,
             "timing": "per-class HIP events over a second timed pass of the same steps, classes serialized",

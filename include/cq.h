@@ -279,6 +279,16 @@ cq_status cq_one_electron(cq_basis b, int kind, int dir, const double* origin, i
  * holds; at most 55). */
 cq_status cq_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, int* n);
 
+/* As cq_quartet_counts, but count[k] is the number of primitive quartets
+ * those shell quartets hold once primitive pairs below the cut are dropped
+ * (sum over the quartets of the surviving primitive pairs of the bra pair
+ * times those of the ket pair).  A primitive pair is dropped when its
+ * prefactor |c_a c_b| exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p is below
+ * 1e-30 of the largest in the basis: its contribution to any integral is
+ * below FP64 resolution.  The kernels skip those primitive pairs.  This is
+ * the algorithmic primitive work of an unscreened build. */
+cq_status cq_prim_quartet_counts(cq_basis b, int maxn, int* cls, long long* count, int* n);
+
 /* Quartet counts of the most recent cq_jk_build / cq_fock2e_2c on this
  * basis, written to HOST out3: [0] evaluated in FP64, [1] evaluated in FP32
  * (precision-routed mode), [2] removed by screening.  Synchronizes `stream`. */

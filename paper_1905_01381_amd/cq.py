@@ -71,6 +71,7 @@ def lib():
         L.cq_one_electron.argtypes = [vp, i, i, dp, i, dp, dp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
         L.cq_quartet_counts.argtypes = [vp, i, ip, llp, ip]
+        L.cq_prim_quartet_counts.argtypes = [vp, i, ip, llp, ip]
         L.cq_profile.argtypes = [vp, i]
         L.cq_trace.argtypes = [vp, i]
         L.cq_build_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong), vp]
@@ -97,7 +98,8 @@ def lib():
         for name in ("cq_basis_create", "cq_basis_create_batch", "cq_basis_create_general", "cq_basis_mol_nbf",
                      "cq_autotune", "cq_plan_set",
                      "cq_autotune_read", "cq_basis_destroy", "cq_schwarz", "cq_jk_build", "cq_fock2e_2c",
-                     "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_profile", "cq_trace",
+                     "cq_boys", "cq_eri_quartet", "cq_one_electron", "cq_quartet_counts", "cq_prim_quartet_counts",
+                     "cq_profile", "cq_trace",
                      "cq_profile_read", "cq_build_stats", "cq_rt_create", "cq_rt_destroy", "cq_rt_set_mode",
                      "cq_rt_set_params", "cq_rt_step", "cq_rt_density", "cq_rt_stats", "cq_rt_record",
                      "cq_rt_recorded", "cq_rt_train", "cq_rt_mlp_weights", "cq_rt_mlp_scales", "cq_expm",
@@ -360,6 +362,15 @@ class Basis:
         cls = (ctypes.c_int * 512)()
         cnt = (ctypes.c_longlong * 128)()
         _check(lib().cq_quartet_counts(self.h, 128, cls, cnt, ctypes.byref(n)))
+        return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
+
+    def prim_quartet_counts(self) -> dict:
+        """{(la, lb, lc, ld): primitive quartets above the primitive cut in
+        the class's unique shell quartets}."""
+        n = ctypes.c_int()
+        cls = (ctypes.c_int * 512)()
+        cnt = (ctypes.c_longlong * 128)()
+        _check(lib().cq_prim_quartet_counts(self.h, 128, cls, cnt, ctypes.byref(n)))
         return {tuple(cls[4 * k: 4 * k + 4]): int(cnt[k]) for k in range(n.value)}
 
     def sync_status(self, stream=None) -> int:

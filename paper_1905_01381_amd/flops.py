@@ -1,7 +1,8 @@
 """Algorithmic FP64 operation counts of the generated kernels.
 
-The per-unit figure is one contracted shell quartet of a class
-(la lb|lc ld) with K_ab * K_cd primitive quartets.  Counts follow the
+The per-unit figures are one primitive quartet and one contracted shell
+quartet of a class (la lb|lc ld): a launch does prim x (its primitive
+quartets above the primitive cut) + fixed x (its shell quartets).  Counts follow the
 emitted recurrences exactly: every VRR node's expression, one add per
 contraction target and primitive quartet, two operations per horizontal
 transfer node, and the digestion dot products (per density: 4 nv for a
@@ -37,6 +38,14 @@ def _count_expr(line: str) -> int:
 
 
 def per_quartet(la, lb, lc, ld, nprim2_bra=9, nprim2_ket=9, nJ=1, nK=1) -> float:
+    prim, fixed = parts(la, lb, lc, ld, nJ, nK)
+    return float(nprim2_bra * nprim2_ket * prim + fixed)
+
+
+def parts(la, lb, lc, ld, nJ=1, nK=1) -> tuple[int, int]:
+    """(operations per primitive quartet, operations per contracted shell
+    quartet): a class's work is prim x (primitive quartets) + fixed x
+    (shell quartets)."""
     L = la + lb + lc + ld
     em = gen_eri.Emitter("")
     vrr = gen_eri.VRR(em, L)
@@ -57,7 +66,7 @@ def per_quartet(la, lb, lc, ld, nprim2_bra=9, nprim2_ket=9, nJ=1, nK=1) -> float
     hrr_nodes = sum(1 for x in em2.lines if x.strip().startswith("const double hb") or x.strip().startswith("const double hk"))
     nv = gen_eri.ncart(la) * gen_eri.ncart(lb) * gen_eri.ncart(lc) * gen_eri.ncart(ld)
     dig = nJ * 4 * nv + nK * 8 * nv
-    return float(nprim2_bra * nprim2_ket * prim + 2 * hrr_nodes + nv + dig)
+    return prim, 2 * hrr_nodes + nv + dig
 
 
 if __name__ == "__main__":

@@ -94,7 +94,11 @@ def test_f_schwarz_and_one_electron(fcase, torch_cuda):
     w, ob, gb, _ = fcase
     Q = gb.schwarz().cpu().numpy()
     Qr = ob.schwarz()
-    assert rel_err(Q, Qr) < 1e-12
+    # diagonal blocks from two FP64 algorithms (product-centred recurrence
+    # summed over primitives here, Hermite expansion in the oracle): within
+    # 2e-12 of the largest factor; 1e-11 is kept, the block bar of the s-d
+    # classes
+    assert rel_err(Q, Qr) < 1e-11
     for kind in ("overlap", "kinetic"):
         assert rel_err(gb.one_electron(kind).cpu().numpy(), ob.one_electron(kind)) < 1e-12, kind
     got = gb.one_electron("dipole", direction=0, origin=(0.1, 0.2, -0.3)).cpu().numpy()
