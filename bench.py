@@ -87,12 +87,15 @@ def parse():
 
 
 def kernel_source_hash(cls: str) -> str:
-    """sha256 of a class's generated kernel source and the common header it
-    includes (what a counter profile of that kernel was taken on)."""
+    """sha256 of a class's generated kernel source, the common header it
+    includes and the host code that builds its inputs (pair records,
+    primitive cut, task lists): what a counter profile of that kernel was
+    taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1905_01381_amd", "csrc")
-    for p in (os.path.join(csrc, "gen", f"eri_{cls}.hip"), os.path.join(csrc, "eri_common.hpp")):
+    for p in (os.path.join(csrc, "gen", f"eri_{cls}.hip"), os.path.join(csrc, "eri_common.hpp"),
+              os.path.join(csrc, "cq_api.hip")):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
