@@ -133,6 +133,9 @@ struct PairSet {
     // Primitive-pair records [npair][nprim2][10]: p, K, 1/(2p), Px, Py, Pz,
     // PAx, PAy, PAz, 0 (one lane reads its record with five 16-byte loads).
     const double* rec;  // K = c_a c_b exp(-alpha beta/p |AB|^2) sqrt(2) pi^{5/4} / p
+    // Records of a pair with K != 0 (above the primitive cut); they come
+    // first, so records nsig .. nprim2-1 of the pair all have K = 0.
+    const int* nsig;
 };
 
 // One molecule of a basis (a batch holds many): its shells and functions are
@@ -321,6 +324,16 @@ __device__ __forceinline__ double wave_max(double v)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// min(cap, largest v over the 64 lanes), read into a scalar register so that
+// a loop bounded by it is wave-uniform.  Every lane of the wave must be
+// active.
+__device__ __forceinline__ int wave_max_bound(int v, int cap)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v < cap ? v : cap);
 }
 
 

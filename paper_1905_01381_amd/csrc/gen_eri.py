@@ -46,6 +46,13 @@ def T_() -> str:
     return PREC["T"]
 
 
+# Trip counts of the primitive-pair loops.  The J/K kernels run each loop to
+# the largest count of primitive pairs above the primitive cut among the
+# wave's active lanes (a wave-uniform bound, nkp / nkq, computed per step);
+# the block kernel, whose tail lanes have returned, runs every record.
+LOOP = {"kp": "bra.nprim2", "kq": "ket.nprim2"}
+
+
 def lit(x) -> str:
     """A numeric literal of the current precision."""
     v = repr(float(x))
@@ -197,7 +204,7 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
     coefficients (the loops are closed by the caller)."""
     L = la + lb + lc + ld
     T = T_()
-    out("for (int kp = 0; kp < bra.nprim2; ++kp) {")
+    out(f"for (int kp = 0; kp < {LOOP['kp']}; ++kp) {{")
     out("  const double2* br = (const double2*)(bra.rec + ((size_t)ib * bra.nprim2 + kp) * 10);")
     out("  const double2 b0 = br[0];")
     out(f"  const {T} p = b0.x;")
@@ -209,7 +216,7 @@ def emit_prim_header(out: Emitter, la, lb, lc, ld):
     if la + lb > 0:
         out("  const double2 b3 = br[3], b4 = br[4];")
         out(f"  const {T} PAx = b3.x, PAy = b3.y, PAz = b4.x;")
-    out("  for (int kq = 0; kq < ket.nprim2; ++kq) {")
+    out(f"  for (int kq = 0; kq < {LOOP['kq']}; ++kq) {{")
     out("    const double2* kr = (const double2*)(ket.rec + ((size_t)jk * ket.nprim2 + kq) * 10);")
     out("    const double2 k0 = kr[0], k1 = kr[1], k2 = kr[2];")
     out(f"    const {T} q = k0.x;")
@@ -935,10 +942,12 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     set_tile(tile_rows(la, lb, lc, ld))
     body = Emitter("    ")
     dig = Emitter("    ")
+    LOOP.update(kp="nkp", kq="nkq")
     if staged:
         nvrr = emit_staged_eri(body, la, lb, lc, ld)
     else:
         _, nvrr = emit_eri_body(body, la, lb, lc, ld)
+    LOOP.update(kp="bra.nprim2", kq="ket.nprim2")
     set_prec("double")
     if staged:
         emit_staged_digest(dig, la, lb, lc, ld)
@@ -1034,7 +1043,7 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
     o(f"      const bool colv = dval{' && d_idx <= c_idx' if same_cd else ''};")
     o("      bool active = rowv && colv;")
     if same_cls:
-        o("      if (c_idx == a_idx) active = active && b_idx >= d_idx;")
+        o("      if (c_idx == a_idx) active = active && b >= d;  // shell numbers: the b list is ordered per a")
     o(f"      const int jk = mc.ppos[spair(mc, c, colv ? d : {'c' if same_cd else 'd'})];")
     o("      const int fc = ket.fa[jk], fd = ket.fb[jk];")
     if kbd or sacc:
@@ -1050,6 +1059,8 @@ def emit_jk_kernel(la, lb, lc, ld, prec: str) -> tuple[str, int, int]:
         o("      if (c == d) deg *= 0.5;")
     if same_cls:
         o("      if (a == c && b == d) deg *= 0.5;")
+    o("      const int nkp = wave_max_bound(active ? bra.nsig[ib] : 0, bra.nprim2);")
+    o("      const int nkq = wave_max_bound(active ? ket.nsig[jk] : 0, ket.nprim2);")
     body.lines = ["  " + x if x else x for x in body.lines]
     o(body.text())
     if not staged:
