@@ -866,8 +866,10 @@ def acc_doubles(la, lb, lc, ld):
 # J'_cd lanes (64/R nc nd nJ).  Measured on the 40-atom two-component build
 # (nK = 8, nJ = 1), every class tried was slower with fewer rows: (dp|ps)
 # 77.6 -> 84.4 ms and (dp|ds) 89.1 -> 96.4 ms at R = 2, (ps|ps) 30.6 -> 32.6
-# and (ds|ps) 52.7 -> 55.3 ms at R = 4, (ds|ds) 35.2 -> 37.9 ms at R = 2; so
-# every class keeps R = 8.
+# and (ds|ps) 52.7 -> 55.3 ms at R = 4, (ds|ds) 35.2 -> 37.9 ms at R = 2.
+# More rows were slower too, even with each a's b partners ordered by their
+# surviving primitive pairs (16 b x 4 d): (ps|ss) 26.7 -> 30.1 ms, (pp|ss)
+# 15.6 -> 21.3, (ss|ss) 6.6 -> 8.6.  So every class keeps R = 8.
 TILE_ROWS = {}
 
 
